@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Throughput of the phase-linking hot path on one MI355X.
+
+One step = amplitude statistics -> GLRT SHP masks -> sample coherence ->
+EMI/EVD phase linking -> compressed SLC over one synthetic mini-stack that is
+already resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload burst|scale|tiny]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBps": 8000.0,
+    "bf16_mfma_TFLOPs": 2500.0,
+    "fp32_mfma_TFLOPs": 157.3,
+    "fp32_valu_TFLOPs": 78.6,  # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, no packed FP32
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="burst")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    return ap.parse_args()
+
+
+class Path:
+    """The hot path on one resident stack with pre-built geometry."""
+
+    def __init__(self, plink, wl, stack, precision):
+        self.plink, self.wl, self.z, self.prec = plink, wl, stack, precision
+        self.ref = max(0, wl.n_comp - 1)
+        self.first_real = wl.n_comp
+        self.real = stack[wl.n_comp:] if wl.n_comp else stack
+
+    def stats(self):
+        return self.plink.amplitude_stats(self.real)
+
+    def glrt(self, st):
+        return self.plink.shp_select(st[0], st[1], self.wl.n_new, self.wl.window, self.wl.alpha)
+
+    def coherence(self, m):
+        return self.plink.estimate_coherence(self.z, m[0], self.wl.window, precision=self.prec)
+
+    def link(self, coh):
+        return self.plink.phase_link(coh, ref=self.ref)
+
+    def compress(self, ln):
+        oR, oC = self.wl.out_shape
+        return self.plink.compress_ministack(self.z, self.first_real, self.wl.window,
+                                             ln[0].view(self.wl.N, oR, oC))
+
+    def step(self):
+        st = self.stats()
+        m = self.glrt(st)
+        coh = self.coherence(m)
+        ln = self.link(coh)
+        k = self.compress(ln)
+        return m, coh, ln, k
+
+
+def time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def stage_times(torch, path, steps):
+    """Average device time of each stage, HIP events on the stream the kernels use."""
+    names = ["stats", "glrt", "coherence", "link", "compress"]
+    acc = {n: 0.0 for n in names}
+    for _ in range(steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        ev[0].record()
+        st = path.stats(); ev[1].record()
+        m = path.glrt(st); ev[2].record()
+        coh = path.coherence(m); ev[3].record()
+        ln = path.link(coh); ev[4].record()
+        path.compress(ln); ev[5].record()
+        torch.cuda.synchronize()
+        for i, n in enumerate(names):
+            acc[n] += ev[i].elapsed_time(ev[i + 1])
+    return {n: v / steps for n, v in acc.items()}
+
+
+def algorithmic(wl, shp_sum, P):
+    """Algorithmic bytes and flops of each stage (one launch each)."""
+    R, C, N, M = wl.R, wl.C, wl.N, wl.n_new
+    nw = ((2 * wl.window[0] + 1) * (2 * wl.window[1] + 1) + 31) // 32
+    px = R * C
+    return {
+        "stats": {"bytes": px * M * 8 + px * 16},
+        "glrt": {"bytes": px * 16 + P * nw * 4 + P * 2},
+        # complex MACs over the N(N+1)/2 unique entries of each Hermitian A, 8 flops each
+        "coherence": {"bytes": px * N * 8 + P * nw * 4 + P * N * N * 8,
+                      "flops": shp_sum * (N * (N + 1) // 2) * 8},
+        "link": {"bytes": P * N * N * 8 + P * N * 8 + P * 5},
+        "compress": {"bytes": px * M * 8 + P * N * 8 + px * 8},
+    }
+
+
+def cpu_baseline(wl_name, seed):
+    """The FP64 oracle on a bounded crop of the same workload (host cores)."""
+    import numpy as np
+
+    import synth
+    from oracle import plink_oracle as O
+    wl = synth.crop(wl_name, 192 if wl_name != "tiny" else 64, 768 if wl_name != "tiny" else 64)
+    z = synth.make_stack(wl, seed=seed).numpy()
+    t0, c0 = time.perf_counter(), time.process_time()
+    r = O.link_ministack(z, wl.n_comp, wl.window, wl.alpha, max(0, wl.n_comp - 1))
+    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    P = int(np.prod(wl.out_shape))
+    return {"value": P / wall, "unit": "pixels/s", "cores": max(1, round(cpu / wall)),
+            "kind": "oracle",
+            "sample": f"{wl.R}x{wl.C} crop of the {wl_name} workload (N={wl.N}, window "
+                      f"{wl.window}), {P} output pixels, {wall:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(this build runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2511_12051_amd as plink
+    import synth
+    plink.load()
+    wl = synth.WORKLOADS[args.workload]
+    print(f"[bench] generating {wl.name} {wl.N}x{wl.R}x{wl.C} on cuda:0", file=sys.stderr, flush=True)
+    stack = synth.make_stack(wl, seed=args.seed, device="cuda")
+    torch.cuda.synchronize()
+    oR, oC = wl.out_shape
+    P = oR * oC
+
+    results = {}
+    precs = [args.precision] + ([] if args.no_compare else [p for p in ("bf16", "fp32") if p != args.precision])
+    for prec in precs:
+        path = Path(plink, wl, stack, prec)
+        print(f"[bench] {prec}: warmup {args.warmup}, steps {args.steps}", file=sys.stderr, flush=True)
+        ms = time_steps(torch, path.step, args.steps, args.warmup)
+        stages = stage_times(torch, path, max(3, args.steps // 2))
+        m, coh, ln, k = path.step()
+        torch.cuda.synchronize()
+        shp_sum = int(m[1].to(torch.int32).sum().item())
+        flags = ln[2].cpu().numpy()
+        results[prec] = {"ms": ms, "stages": stages, "shp_sum": shp_sum,
+                         "evd_frac": float(np.mean(flags == 1)), "invalid_frac": float(np.mean(flags == 2))}
+        print(f"[bench] {prec}: {ms:.3f} ms/step, stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}",
+              file=sys.stderr, flush=True)
+
+    main_r = results[args.precision]
+    alg = algorithmic(wl, main_r["shp_sum"], P)
+    st = main_r["stages"]
+    dom = max(st, key=st.get)
+    t = st[dom] * 1e-3
+    if dom == "coherence" and args.precision == "bf16":
+        roof = {"bound": "mfma", "achieved": alg[dom]["flops"] / t / 1e12,
+                "peak": PEAK["bf16_mfma_TFLOPs"], "unit": "TFLOP/s"}
+    elif dom == "coherence":
+        roof = {"bound": "mfma", "achieved": alg[dom]["flops"] / t / 1e12,
+                "peak": PEAK["fp32_mfma_TFLOPs"], "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": alg[dom]["bytes"] / t / 1e9, "peak": PEAK["hbm_GBps"],
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+
+    line = {
+        "metric": "phase-linked pixels/sec at N=15/25 within 1e-3 rad of FP64 oracle; mixed vs FP32",
+        "value": P / (main_r["ms"] * 1e-3),
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x2->f32" if args.precision == "bf16" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.R}x{wl.C} grid, N={wl.N} ({wl.n_comp} compressed + "
+                               f"{wl.n_new} new), half-window {wl.window[0]}x{wl.window[1]}, "
+                               f"stride {wl.window[2]}x{wl.window[3]}, {P} output pixels",
+                   "precision": args.precision},
+        "stage_ms": {k: round(v, 4) for k, v in st.items()},
+        "roofline": roof,
+    }
+    for prec, r in results.items():
+        if prec != args.precision:
+            line[f"{prec}_value"] = P / (r["ms"] * 1e-3)
+            line[f"{prec}_ms_per_step"] = r["ms"]
+            line[f"{prec}_stage_ms"] = {k: round(v, 4) for k, v in r["stages"].items()}
+            line["mixed_speedup_vs_fp32"] = (results["fp32"]["ms"] / results["bf16"]["ms"]
+                                             if "fp32" in results and "bf16" in results else None)
+    line["evd_fraction"] = main_r["evd_frac"]
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a crop (host cores)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

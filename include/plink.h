@@ -1,0 +1,215 @@
+/*
+ * plink.h - C ABI of the MI355X (gfx950) sequential phase-linking library.
+ *
+ * Method: Staniewicz et al., "Near-Real-Time InSAR Phase Estimation for
+ * Large-Scale Surface Displacement Monitoring" (arXiv 2511.12051).  Each call
+ * below names the passage of the paper that defines what it computes.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Array arguments are DEVICE pointers into memory owned by the caller (for
+ *    example PyTorch tensors); the library never frees or keeps them.  Host
+ *    pointers are marked "host".
+ *  - Complex numbers are pl_c64 = {float re; float im;} (complex64 layout).
+ *  - Rasters are image-major and row-major: a stack is [N][R][C], an image
+ *    (plane) is [R][C], so consecutive columns are consecutive in memory.
+ *  - Every compute call enqueues its kernels on `stream` (a hipStream_t;
+ *    NULL = the legacy default stream) and returns without waiting for them.
+ *    Argument errors are detected before anything is enqueued; a launch
+ *    failure is returned as PL_ERR_HIP.  pl_last_error() gives a message.
+ *  - Window geometry (pl_window): the SHP search window of a pixel holds all
+ *    pixels within half_x columns and half_y rows of it, i.e. a
+ *    (2*half_x+1) x (2*half_y+1) box (supplement table of SHP window sizes);
+ *    pixels outside the image are not part of it.  Phase linking runs on a
+ *    decimated output grid of oR = R / stride_y rows and oC = C / stride_x
+ *    columns whose pixel (oy, ox) sits at image pixel
+ *    (oy*stride_y + stride_y/2, ox*stride_x + stride_x/2) (Sec. 4: linking
+ *    at every 6th and 3rd pixel from the centre of each decimation window).
+ *  - SHP masks are [oR][oC][nwords] uint32 with nwords = ceil(W/32),
+ *    W = (2*half_x+1)*(2*half_y+1); bit b (word b/32, bit b%32) is window
+ *    offset b in row-major order starting at (-half_y, -half_x).
+ *  - Stacks hold at most PL_MAX_N images; compressed SLCs come first, in
+ *    chronological order, then the real SLCs of the mini-stack (Sec. 2.2).
+ *  - Optional `counters` arguments are device arrays of PL_NUM_COUNTERS
+ *    uint64 (caller-owned, caller-zeroed) that the kernels add to.
+ */
+#ifndef PLINK_H
+#define PLINK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PL_MAX_N 32
+#define PL_MAX_WINDOW 1024 /* largest W = (2hx+1)(2hy+1) */
+
+typedef void* pl_stream; /* hipStream_t */
+
+typedef struct {
+    float re;
+    float im;
+} pl_c64;
+
+typedef enum {
+    PL_OK = 0,
+    PL_ERR_INVALID_ARG = 1, /* NULL pointer, bad enum value, non-positive size */
+    PL_ERR_SHAPE = 2,       /* sizes inconsistent with each other or the window */
+    PL_ERR_UNSUPPORTED = 3, /* outside what the kernels handle (e.g. N > PL_MAX_N) */
+    PL_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+    PL_ERR_WORKSPACE = 5,   /* buffer too small */
+    PL_ERR_STATE = 6        /* driver state or checkpoint does not match */
+} pl_status;
+
+typedef struct {
+    int32_t half_x, half_y;     /* search half-window (columns, rows) */
+    int32_t stride_x, stride_y; /* output decimation (columns, rows) */
+} pl_window;
+
+typedef enum {
+    PL_PREC_FP32 = 0,      /* coherence accumulated with FP32 products */
+    PL_PREC_SPLIT_BF16 = 1 /* products of hi+lo BF16 splits, FP32 accumulation */
+} pl_precision;
+
+typedef enum {
+    PL_LINK_EMI = 0, /* EMI, EVD where the |C| inversion fails */
+    PL_LINK_EVD = 1  /* EVD for every pixel */
+} pl_link_method;
+
+/* per-pixel flags written by phase linking */
+enum { PL_FLAG_EMI = 0, PL_FLAG_EVD = 1, PL_FLAG_INVALID = 2 };
+
+/* indices into the optional counters array */
+enum {
+    PL_CNT_GLRT_BAND = 0,     /* pair tests with |T - threshold| < 1e-9 */
+    PL_CNT_GLRT_RECHECK = 1,  /* pair tests decided by the exact log form */
+    PL_CNT_EVD = 2,           /* pixels that fell back to EVD */
+    PL_CNT_INVALID = 3,       /* pixels flagged invalid */
+    PL_CNT_NOT_CONVERGED = 4, /* eigenvector iterations that hit the cap */
+    PL_CNT_SHIFT_RETRY = 5,   /* shifts rejected by the inertia check */
+    PL_CNT_ITERS = 6,         /* total eigenvector iterations */
+    PL_NUM_COUNTERS = 8
+};
+
+/* ---------------------------------------------------------------- library */
+const char* pl_version(void);
+const char* pl_status_string(pl_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* pl_last_error(void);
+/* Output grid of an R x C image (host helper; no device work). */
+pl_status pl_output_grid(int64_t R, int64_t C, pl_window w, int64_t* oR, int64_t* oC);
+/* Number of uint32 words per SHP mask, or 0 for an invalid window. */
+int32_t pl_mask_words(pl_window w);
+
+/* -------------------------------------------------- amplitude statistics
+ * Per-pixel mean and population variance of |z| over the M images of `slc`
+ * [M][R][C] (Sec. 3.1: mu_A and sigma_A of the amplitude dispersion; the
+ * ancillary statistics stored with each compressed SLC).  Accumulated in
+ * FP64.  mean, var: [R][C] float64. */
+pl_status pl_amplitude_stats(const pl_c64* slc, int32_t M, int64_t R, int64_t C, double* mean,
+                             double* var, pl_stream stream);
+
+/* Pooled mean and variance of G groups of statistics (eq. merged-mean and
+ * eq. merged-variance).  means, vars: [G][R][C] float64; weights: host [G],
+ * positive.  mean_out, var_out: [R][C]; they may alias group 0. */
+pl_status pl_merge_amplitude_stats(const double* means, const double* vars, const double* weights,
+                                   int32_t G, int64_t R, int64_t C, double* mean_out,
+                                   double* var_out, pl_stream stream);
+
+/* ------------------------------------------------------- SHP selection
+ * GLRT selection of statistically homogeneous pixels (Sec. 3.1: a GLRT on
+ * amplitude means and variances).  With the Rayleigh scale
+ * s = (mean^2 + var)/2 of each pixel and n = n_eff samples,
+ * T = 2n [2 ln((s_p+s_q)/2) - ln s_p - ln s_q]; q is an SHP of p iff
+ * T <= chi2_1^{-1}(1 - alpha).  A pixel is always an SHP of itself; a pixel
+ * whose s is not finite and positive is an SHP of no other pixel and has only
+ * itself.  The decision is taken in FP64; tests within 1e-9 of the threshold
+ * are counted in counters[PL_CNT_GLRT_BAND].
+ * mask: [oR][oC][nwords] uint32; count: [oR][oC] uint16 (SHPs incl. itself);
+ * counters: optional. */
+pl_status pl_shp_select(const double* mean, const double* var, int64_t R, int64_t C, double n_eff,
+                        pl_window w, double alpha, uint32_t* mask, uint16_t* count,
+                        uint64_t* counters, pl_stream stream);
+
+/* --------------------------------------------------- sample coherence
+ * Sample coherence over each output pixel's SHPs (eq. sample-coherence),
+ * A_mn = sum_{q in Omega} z_m(q) conj(z_n(q)), normalised to unit diagonal:
+ * C_mn = A_mn / sqrt(A_mm A_nn).  stack: [N][R][C]; mask as above;
+ * coh: [oR*oC][N][N] full Hermitian matrices, row-major.  A pixel where some
+ * image has zero power over its SHPs gets an all-NaN matrix.  prec selects
+ * plain FP32 products or hi+lo BF16 split products on the matrix cores. */
+pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                                const uint32_t* mask, pl_precision prec, pl_c64* coh,
+                                pl_stream stream);
+
+/* ------------------------------------------------------- phase linking
+ * EMI phase linking (Sec. 3.2, eq. emi-eigenvalue-problem): the eigenvector
+ * of the smallest eigenvalue of |C|^{-1} o C, found by shifted inverse
+ * iteration starting from the shift 0.99; |C| is inverted in FP64 and when an
+ * LDL^T pivot of |C| is <= 1e-6 (inversion fails) the pixel falls back to EVD,
+ * the eigenvector of the largest eigenvalue of C.  The result is referenced to
+ * image ref_idx (Sec. 2.1: multiplied by conj(zeta_r)) and returned as unit
+ * phasors.  coh: [npix][N][N]; phasors: [N][npix] (phasors[ref_idx] = 1);
+ * lambda: [npix] or NULL (eigenvalue of the vector: lambda_min of
+ * |C|^{-1} o C for EMI, lambda_max of C for EVD); flags: [npix] or NULL
+ * (PL_FLAG_*); invalid pixels (non-finite C) get phasors 1.
+ * counters: optional. */
+pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
+                        pl_link_method method, pl_c64* phasors, float* lambda, uint8_t* flags,
+                        uint64_t* counters, pl_stream stream);
+
+/* ------------------------------------------------------ compressed SLC
+ * Compressed SLC of a mini-stack (Sec. 2.2): kappa = zeta^H z over the real
+ * images first_real..N-1, i.e. kappa(p) = sum_i conj(zeta_i(b(p))) z_i(p),
+ * where b(p) is the output pixel whose decimation block holds p
+ * (b = (min(y/stride_y, oR-1), min(x/stride_x, oC-1))).
+ * stack: [N][R][C]; phasors: [N][oR][oC]; kappa: [R][C]. */
+pl_status pl_compress_ministack(const pl_c64* stack, int32_t N, int32_t first_real, int64_t R,
+                                int64_t C, pl_window w, const pl_c64* phasors, pl_c64* kappa,
+                                pl_stream stream);
+
+/* ----------------------------------------------- sequential estimator
+ * The mini-stack reference scheme of Sec. 2.2 (Fig. 1, "proposed
+ * approach"): mini-stack k is [kappa_{k-K} .. kappa_{k-1} | M new SLCs]
+ * with K = min(k, K_max); it is referenced to the most recent compressed SLC
+ * (to its first image for k = 0), so every output is referenced to the first
+ * date; earlier mini-stacks are never re-estimated.  The amplitude
+ * statistics of mini-stacks k-K..k are merged with weights M
+ * (eq. merged-mean/-variance) and n_eff = (K+1) M feeds the GLRT. */
+typedef struct pl_seq pl_seq;
+
+typedef struct {
+    int64_t R, C;       /* image size */
+    int32_t M;          /* new SLCs per mini-stack (1..PL_MAX_N) */
+    int32_t K_max;      /* compressed SLCs kept (M + K_max <= PL_MAX_N) */
+    pl_window w;
+    double alpha;       /* GLRT false-alarm rate */
+    int32_t precision;  /* pl_precision */
+    int32_t method;     /* pl_link_method */
+} pl_seq_params;
+
+/* Creates a driver; allocates its device state on the current device. */
+pl_status pl_seq_create(const pl_seq_params* params, pl_seq** out);
+pl_status pl_seq_destroy(pl_seq* s);
+/* Number of mini-stacks pushed so far (host). */
+pl_status pl_seq_count(const pl_seq* s, int64_t* count);
+/* Processes the next mini-stack.  new_slcs: [M][R][C]; phasors_out:
+ * [M][oR][oC] linked phasors of the new SLCs, referenced to the first date;
+ * kappa_out: [R][C] or NULL (copy of the new compressed SLC); flags_out:
+ * [oR*oC] or NULL; counters optional. */
+pl_status pl_seq_push(pl_seq* s, const pl_c64* new_slcs, pl_c64* phasors_out, pl_c64* kappa_out,
+                      uint8_t* flags_out, uint64_t* counters, pl_stream stream);
+/* Size in bytes of a checkpoint (compressed SLCs, statistics, counters). */
+pl_status pl_seq_state_size(const pl_seq* s, size_t* bytes);
+/* Writes the checkpoint into host memory (synchronises `stream`). */
+pl_status pl_seq_save(const pl_seq* s, void* host_buf, size_t bytes, pl_stream stream);
+/* Restores a checkpoint written by a driver with the same parameters. */
+pl_status pl_seq_load(pl_seq* s, const void* host_buf, size_t bytes, pl_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLINK_H */

@@ -285,13 +285,15 @@ def phase_link(Cmat, ref=0, method="emi", valid=None, tau=TAU_PIVOT):
         w, V = np.linalg.eigh(H)
         v[e] = V[:, :, 0]
         lam[e] = w[:, 0]
-        cond[e] = np.abs(w).max(axis=1) / (w[:, 1] - w[:, 0])
+        if N > 1:
+            cond[e] = np.abs(w).max(axis=1) / (w[:, 1] - w[:, 0])
     f = valid & use_evd
     if f.any():
         w, V = np.linalg.eigh(Csafe[f])
         v[f] = V[:, :, -1]
         lam[f] = w[:, -1]
-        cond[f] = np.abs(w).max(axis=1) / (w[:, -1] - w[:, -2])
+        if N > 1:
+            cond[f] = np.abs(w).max(axis=1) / (w[:, -1] - w[:, -2])
     vr = v[:, ref]
     valid &= np.abs(vr) > 0
     # multiplying by conj(zeta_r) sets phi_r = 0 (Sec. 2.1); the positive factor
@@ -310,6 +312,35 @@ def phase_link(Cmat, ref=0, method="emi", valid=None, tau=TAU_PIVOT):
         "min_pivot": min_piv,
         "cond": cond,
     }
+
+
+def phase_sensitivity(Cmat, ref=0, method="emi", n_probe=4, eps=1e-7, seed=0):
+    """Statistical estimate of how far the linked phases move per unit change
+    of the entries of C (test infrastructure, not part of the method).
+
+    Each probe adds a random Hermitian perturbation with |E_mn| = eps off the
+    diagonal (the diagonal stays 1) and re-links in FP64; the estimate is the
+    largest wrapped phase change over probes and images divided by eps
+    (small-sample statistical condition estimation).  Pixels whose EMI/EVD
+    decision flips under a probe, or that are invalid, get inf.
+    """
+    Cm = np.asarray(Cmat, dtype=np.complex128)
+    P, N, _ = Cm.shape
+    base = phase_link(Cm, ref=ref, method=method)
+    rng = np.random.default_rng(seed)
+    sens = np.zeros(P)
+    iu = np.triu_indices(N, 1)
+    for _ in range(n_probe):
+        E = np.zeros((P, N, N), dtype=np.complex128)
+        th = rng.uniform(-np.pi, np.pi, (P, len(iu[0])))
+        E[:, iu[0], iu[1]] = eps * np.exp(1j * th)
+        E = E + np.conj(np.swapaxes(E, 1, 2))
+        out = phase_link(Cm + E, ref=ref, method=method)
+        d = np.abs(wrap(out["phase"] - base["phase"])).max(axis=0) / eps
+        d[out["flag"] != base["flag"]] = np.inf
+        sens = np.maximum(sens, d)
+    sens[base["flag"] == FLAG_INVALID] = np.inf
+    return sens
 
 
 # --------------------------------------------------------------------------

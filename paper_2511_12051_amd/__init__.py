@@ -1,0 +1,303 @@
+"""Python binding of libplink (MI355X / gfx950 sequential phase linking).
+
+Argument marshalling only: every step runs in the library's HIP kernels on the
+tensors' device, enqueued on torch's current stream.  There is no CPU path:
+if the shared library is missing or no GPU is present the calls raise.
+
+Method: Staniewicz et al., arXiv 2511.12051 (sequential EMI phase linking
+with compressed SLCs).  The C declarations, with the passages they follow,
+are in include/plink.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "PlinkError", "load", "library_path", "output_grid", "mask_words", "amplitude_stats",
+    "merge_amplitude_stats", "shp_select", "estimate_coherence", "phase_link",
+    "compress_ministack", "Sequential", "new_counters", "COUNTERS", "FLAG_EMI", "FLAG_EVD",
+    "FLAG_INVALID", "MAX_N",
+]
+
+MAX_N = 32
+FLAG_EMI, FLAG_EVD, FLAG_INVALID = 0, 1, 2
+#: names of the counters array entries (index = position)
+COUNTERS = ("glrt_band", "glrt_recheck", "evd", "invalid", "not_converged", "shift_retry", "iters")
+_PREC = {"fp32": 0, "bf16": 1, "split_bf16": 1}
+_METHOD = {"emi": 0, "evd": 1}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.environ.get("PLINK_LIBRARY", os.path.join(_HERE, "libplink.so"))
+
+
+class PlinkError(RuntimeError):
+    pass
+
+
+class _Window(ctypes.Structure):
+    _fields_ = [("half_x", ctypes.c_int32), ("half_y", ctypes.c_int32),
+                ("stride_x", ctypes.c_int32), ("stride_y", ctypes.c_int32)]
+
+
+class _SeqParams(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int64), ("C", ctypes.c_int64), ("M", ctypes.c_int32),
+                ("K_max", ctypes.c_int32), ("w", _Window), ("alpha", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("method", ctypes.c_int32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+_SIGNATURES = {
+    "pl_version": (ctypes.c_char_p, []),
+    "pl_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "pl_last_error": (ctypes.c_char_p, []),
+    "pl_output_grid": (ctypes.c_int, [_I64, _I64, _Window, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "pl_mask_words": (_I32, [_Window]),
+    "pl_amplitude_stats": (ctypes.c_int, [_P, _I32, _I64, _I64, _P, _P, _P]),
+    "pl_merge_amplitude_stats": (ctypes.c_int, [_P, _P, ctypes.POINTER(_D), _I32, _I64, _I64, _P, _P, _P]),
+    "pl_shp_select": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _Window, _D, _P, _P, _P, _P]),
+    "pl_estimate_coherence": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, ctypes.c_int, _P, _P]),
+    "pl_phase_link": (ctypes.c_int, [_P, _I32, _I64, _I32, ctypes.c_int, _P, _P, _P, _P, _P]),
+    "pl_compress_ministack": (ctypes.c_int, [_P, _I32, _I32, _I64, _I64, _Window, _P, _P, _P]),
+    "pl_seq_create": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(_P)]),
+    "pl_seq_destroy": (ctypes.c_int, [_P]),
+    "pl_seq_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
+    "pl_seq_push": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "pl_seq_state_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "pl_seq_save": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "pl_seq_load": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+}
+
+
+def load():
+    """Loads libplink.so (after torch, so both use torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise PlinkError(f"{path} not built: run python -m paper_2511_12051_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        lib = load()
+        msg = lib.pl_last_error().decode()
+        raise PlinkError(f"{what}: {lib.pl_status_string(status).decode()}: {msg}")
+
+
+def _win(window) -> _Window:
+    hx, hy, sx, sy = (int(v) for v in window)
+    return _Window(hx, hy, sx, sy)
+
+
+def _stream(t: torch.Tensor):
+    if t.device.type != "cuda":
+        raise PlinkError("tensors must live on a GPU (no CPU path)")
+    return _P(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else _P(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, ndim, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.dim() != ndim:
+        raise PlinkError(f"{name}: expected a {ndim}-d {dtype} tensor")
+    if not t.is_contiguous():
+        raise PlinkError(f"{name}: tensor must be contiguous")
+    if t.device.type != "cuda":
+        raise PlinkError(f"{name}: tensor must live on a GPU (no CPU path)")
+
+
+def output_grid(R: int, C: int, window):
+    lib = load()
+    oR, oC = _I64(), _I64()
+    _check(lib.pl_output_grid(int(R), int(C), _win(window), ctypes.byref(oR), ctypes.byref(oC)),
+           "output_grid")
+    return oR.value, oC.value
+
+
+def mask_words(window) -> int:
+    n = load().pl_mask_words(_win(window))
+    if n <= 0:
+        raise PlinkError("mask_words: invalid window")
+    return n
+
+
+def new_counters(device="cuda"):
+    """Zeroed device counter array (see COUNTERS for the entries)."""
+    return torch.zeros(8, dtype=torch.int64, device=device)
+
+
+def amplitude_stats(slc: torch.Tensor):
+    """Mean and population variance of |z| over images: [M,R,C] -> 2 x [R,C] float64."""
+    _need(slc, torch.complex64, 3, "amplitude_stats")
+    M, R, C = slc.shape
+    mean = torch.empty((R, C), dtype=torch.float64, device=slc.device)
+    var = torch.empty_like(mean)
+    _check(load().pl_amplitude_stats(_ptr(slc), M, R, C, _ptr(mean), _ptr(var), _stream(slc)),
+           "amplitude_stats")
+    return mean, var
+
+
+def merge_amplitude_stats(means: torch.Tensor, variances: torch.Tensor, weights):
+    """Pooled statistics of G groups: [G,R,C] x 2 + G weights -> 2 x [R,C]."""
+    _need(means, torch.float64, 3, "merge_amplitude_stats")
+    _need(variances, torch.float64, 3, "merge_amplitude_stats")
+    G, R, C = means.shape
+    w = (_D * G)(*[float(x) for x in weights])
+    mean = torch.empty((R, C), dtype=torch.float64, device=means.device)
+    var = torch.empty_like(mean)
+    _check(load().pl_merge_amplitude_stats(_ptr(means), _ptr(variances), w, G, R, C, _ptr(mean),
+                                           _ptr(var), _stream(means)), "merge_amplitude_stats")
+    return mean, var
+
+
+def shp_select(mean: torch.Tensor, var: torch.Tensor, n_eff: float, window, alpha: float,
+               counters: torch.Tensor | None = None):
+    """GLRT SHP masks: -> (mask int32 [oR,oC,nwords] holding uint32 bits, count int16 [oR,oC])."""
+    _need(mean, torch.float64, 2, "shp_select")
+    _need(var, torch.float64, 2, "shp_select")
+    R, C = mean.shape
+    oR, oC = output_grid(R, C, window)
+    nw = mask_words(window)
+    mask = torch.empty((oR, oC, nw), dtype=torch.int32, device=mean.device)
+    count = torch.empty((oR, oC), dtype=torch.int16, device=mean.device)
+    _check(load().pl_shp_select(_ptr(mean), _ptr(var), R, C, float(n_eff), _win(window),
+                                float(alpha), _ptr(mask), _ptr(count), _ptr(counters),
+                                _stream(mean)), "shp_select")
+    return mask, count
+
+
+def estimate_coherence(stack: torch.Tensor, mask: torch.Tensor, window, precision="fp32"):
+    """Normalised sample coherence over SHPs: -> complex64 [oR*oC, N, N]."""
+    _need(stack, torch.complex64, 3, "estimate_coherence")
+    _need(mask, torch.int32, 3, "estimate_coherence mask")
+    N, R, C = stack.shape
+    oR, oC = output_grid(R, C, window)
+    if tuple(mask.shape) != (oR, oC, mask_words(window)):
+        raise PlinkError("estimate_coherence: mask shape does not match the window")
+    coh = torch.empty((oR * oC, N, N), dtype=torch.complex64, device=stack.device)
+    _check(load().pl_estimate_coherence(_ptr(stack), N, R, C, _win(window), _ptr(mask),
+                                        _PREC[precision], _ptr(coh), _stream(stack)),
+           "estimate_coherence")
+    return coh
+
+
+def phase_link(coh: torch.Tensor, ref: int = 0, method="emi", counters=None):
+    """EMI (EVD fallback) linked phasors: [P,N,N] -> (phasors [N,P], lambda [P], flags uint8 [P])."""
+    _need(coh, torch.complex64, 3, "phase_link")
+    P, N, N2 = coh.shape
+    if N != N2:
+        raise PlinkError("phase_link: matrices must be square")
+    ph = torch.empty((N, P), dtype=torch.complex64, device=coh.device)
+    lam = torch.empty((P,), dtype=torch.float32, device=coh.device)
+    flags = torch.empty((P,), dtype=torch.uint8, device=coh.device)
+    _check(load().pl_phase_link(_ptr(coh), N, P, int(ref), _METHOD[method], _ptr(ph), _ptr(lam),
+                                _ptr(flags), _ptr(counters), _stream(coh)), "phase_link")
+    return ph, lam, flags
+
+
+def compress_ministack(stack: torch.Tensor, first_real: int, window, phasors: torch.Tensor):
+    """Compressed SLC: stack [N,R,C], phasors [N,oR,oC] -> kappa complex64 [R,C]."""
+    _need(stack, torch.complex64, 3, "compress_ministack")
+    N, R, C = stack.shape
+    oR, oC = output_grid(R, C, window)
+    if phasors.dtype != torch.complex64 or phasors.numel() != N * oR * oC or not phasors.is_contiguous():
+        raise PlinkError("compress_ministack: phasors must be contiguous complex64 [N,oR,oC]")
+    kappa = torch.empty((R, C), dtype=torch.complex64, device=stack.device)
+    _check(load().pl_compress_ministack(_ptr(stack), N, int(first_real), R, C, _win(window),
+                                        _ptr(phasors), _ptr(kappa), _stream(stack)),
+           "compress_ministack")
+    return kappa
+
+
+@dataclass
+class SequentialParams:
+    R: int
+    C: int
+    M: int
+    K_max: int
+    window: tuple
+    alpha: float = 1e-3
+    precision: str = "fp32"
+    method: str = "emi"
+
+
+class Sequential:
+    """Sequential estimator (mini-stack reference scheme, compressed SLCs)."""
+
+    def __init__(self, R, C, M, K_max, window, alpha=1e-3, precision="fp32", method="emi",
+                 device="cuda"):
+        lib = load()
+        self.params = SequentialParams(R, C, M, K_max, tuple(window), alpha, precision, method)
+        self.device = torch.device(device)
+        self.out_shape = output_grid(R, C, window)
+        p = _SeqParams(int(R), int(C), int(M), int(K_max), _win(window), float(alpha),
+                       _PREC[precision], _METHOD[method])
+        h = _P()
+        with torch.cuda.device(self.device):
+            _check(lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)), "Sequential")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pl_seq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def count(self) -> int:
+        c = _I64()
+        _check(load().pl_seq_count(self._h, ctypes.byref(c)), "Sequential.count")
+        return c.value
+
+    def push(self, new_slcs: torch.Tensor, counters=None, want_kappa=True, want_flags=False):
+        """Links the next mini-stack [M,R,C]; returns (phasors [M,oR,oC], kappa [R,C] or None,
+        flags [oR,oC] or None)."""
+        p = self.params
+        _need(new_slcs, torch.complex64, 3, "Sequential.push")
+        if tuple(new_slcs.shape) != (p.M, p.R, p.C):
+            raise PlinkError("Sequential.push: expected [M,R,C] new SLCs")
+        oR, oC = self.out_shape
+        ph = torch.empty((p.M, oR, oC), dtype=torch.complex64, device=new_slcs.device)
+        kap = torch.empty((p.R, p.C), dtype=torch.complex64, device=new_slcs.device) if want_kappa else None
+        fl = torch.empty((oR, oC), dtype=torch.uint8, device=new_slcs.device) if want_flags else None
+        _check(load().pl_seq_push(self._h, _ptr(new_slcs), _ptr(ph), _ptr(kap), _ptr(fl),
+                                  _ptr(counters), _stream(new_slcs)), "Sequential.push")
+        return ph, kap, fl
+
+    def save(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(load().pl_seq_state_size(self._h, ctypes.byref(n)), "Sequential.save")
+        buf = ctypes.create_string_buffer(n.value)
+        s = _P(torch.cuda.current_stream(self.device).cuda_stream)
+        _check(load().pl_seq_save(self._h, buf, n.value, s), "Sequential.save")
+        return buf.raw
+
+    def load_state(self, state: bytes):
+        buf = ctypes.create_string_buffer(state, len(state))
+        s = _P(torch.cuda.current_stream(self.device).cuda_stream)
+        _check(load().pl_seq_load(self._h, buf, len(state), s), "Sequential.load_state")

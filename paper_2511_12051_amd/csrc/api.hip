@@ -1,0 +1,194 @@
+// Host side of the C ABI: argument checks, error strings, dispatch.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace plk {
+
+static thread_local char g_last_error[512] = "";
+
+pl_status fail(pl_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+pl_status hip_ok(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PL_OK;
+    return fail(PL_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+pl_status launch_ok(const char* what) { return hip_ok(hipGetLastError(), what); }
+
+bool make_geometry(int64_t R, int64_t C, pl_window w, Geometry* g) {
+    if (R <= 0 || C <= 0) return false;
+    if (w.half_x < 0 || w.half_y < 0 || w.stride_x < 1 || w.stride_y < 1) return false;
+    int64_t wx = 2 * (int64_t)w.half_x + 1, wy = 2 * (int64_t)w.half_y + 1;
+    if (wx * wy > PL_MAX_WINDOW) return false;
+    g->R = R;
+    g->C = C;
+    g->hx = w.half_x;
+    g->hy = w.half_y;
+    g->sx = w.stride_x;
+    g->sy = w.stride_y;
+    g->wx = (int)wx;
+    g->wy = (int)wy;
+    g->W = (int)(wx * wy);
+    g->nw = (g->W + 31) / 32;
+    g->oR = R / w.stride_y;
+    g->oC = C / w.stride_x;
+    return true;
+}
+
+PlaneTable contiguous_planes(const pl_c64* stack, int N, int64_t plane) {
+    PlaneTable t{};
+    for (int i = 0; i < N && i < kMaxN; ++i)
+        t.p[i] = reinterpret_cast<const float2*>(stack) + (int64_t)i * plane;
+    return t;
+}
+
+size_t max_lds_bytes() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return v > 0 ? (size_t)v : 65536;
+}
+
+}  // namespace plk
+
+using namespace plk;
+
+static hipStream_t S(pl_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+#define PL_CHECK(cond, status, ...) \
+    do {                            \
+        if (!(cond)) return fail(status, __VA_ARGS__); \
+    } while (0)
+
+extern "C" {
+
+const char* pl_version(void) { return "plink 0.1 (gfx950)"; }
+
+const char* pl_status_string(pl_status s) {
+    switch (s) {
+        case PL_OK: return "ok";
+        case PL_ERR_INVALID_ARG: return "invalid argument";
+        case PL_ERR_SHAPE: return "inconsistent shape";
+        case PL_ERR_UNSUPPORTED: return "unsupported";
+        case PL_ERR_HIP: return "HIP error";
+        case PL_ERR_WORKSPACE: return "buffer too small";
+        case PL_ERR_STATE: return "state mismatch";
+    }
+    return "unknown status";
+}
+
+const char* pl_last_error(void) { return g_last_error; }
+
+pl_status pl_output_grid(int64_t R, int64_t C, pl_window w, int64_t* oR, int64_t* oC) {
+    Geometry g;
+    PL_CHECK(oR && oC, PL_ERR_INVALID_ARG, "pl_output_grid: NULL output");
+    PL_CHECK(make_geometry(R, C, w, &g), PL_ERR_SHAPE, "pl_output_grid: bad image size or window");
+    *oR = g.oR;
+    *oC = g.oC;
+    return PL_OK;
+}
+
+int32_t pl_mask_words(pl_window w) {
+    Geometry g;
+    if (!make_geometry(1, 1, w, &g)) return 0;
+    return g.nw;
+}
+
+pl_status pl_amplitude_stats(const pl_c64* slc, int32_t M, int64_t R, int64_t C, double* mean,
+                             double* var, pl_stream stream) {
+    PL_CHECK(slc && mean && var, PL_ERR_INVALID_ARG, "pl_amplitude_stats: NULL pointer");
+    PL_CHECK(M >= 1 && M <= kMaxN, PL_ERR_UNSUPPORTED, "pl_amplitude_stats: M=%d outside 1..%d", M, kMaxN);
+    PL_CHECK(R >= 1 && C >= 1, PL_ERR_SHAPE, "pl_amplitude_stats: empty image");
+    PlaneTable t = contiguous_planes(slc, M, R * C);
+    return launch_amp_stats(t, 0, M, R * C, mean, var, S(stream));
+}
+
+pl_status pl_merge_amplitude_stats(const double* means, const double* vars, const double* weights,
+                                   int32_t G, int64_t R, int64_t C, double* mean_out,
+                                   double* var_out, pl_stream stream) {
+    PL_CHECK(means && vars && weights && mean_out && var_out, PL_ERR_INVALID_ARG,
+             "pl_merge_amplitude_stats: NULL pointer");
+    PL_CHECK(G >= 1 && G <= 64, PL_ERR_UNSUPPORTED, "pl_merge_amplitude_stats: G=%d outside 1..64", G);
+    PL_CHECK(R >= 1 && C >= 1, PL_ERR_SHAPE, "pl_merge_amplitude_stats: empty image");
+    for (int i = 0; i < G; ++i)
+        PL_CHECK(weights[i] > 0 && std::isfinite(weights[i]), PL_ERR_INVALID_ARG,
+                 "pl_merge_amplitude_stats: weight %d not positive", i);
+    const double* mp[64];
+    const double* vp[64];
+    for (int i = 0; i < G; ++i) {
+        mp[i] = means + (int64_t)i * R * C;
+        vp[i] = vars + (int64_t)i * R * C;
+    }
+    return launch_merge_stats(mp, vp, weights, G, R * C, mean_out, var_out, S(stream));
+}
+
+pl_status pl_shp_select(const double* mean, const double* var, int64_t R, int64_t C, double n_eff,
+                        pl_window w, double alpha, uint32_t* mask, uint16_t* count,
+                        uint64_t* counters, pl_stream stream) {
+    Geometry g;
+    PL_CHECK(mean && var && mask && count, PL_ERR_INVALID_ARG, "pl_shp_select: NULL pointer");
+    PL_CHECK(make_geometry(R, C, w, &g), PL_ERR_SHAPE, "pl_shp_select: bad image size or window");
+    PL_CHECK(g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE, "pl_shp_select: image smaller than one stride");
+    PL_CHECK(n_eff > 0 && std::isfinite(n_eff), PL_ERR_INVALID_ARG, "pl_shp_select: n_eff must be > 0");
+    PL_CHECK(alpha > 0 && alpha < 1, PL_ERR_INVALID_ARG, "pl_shp_select: alpha must lie in (0, 1)");
+    return launch_shp_select(mean, var, g, n_eff, alpha, mask, count,
+                             reinterpret_cast<unsigned long long*>(counters), S(stream));
+}
+
+pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                                const uint32_t* mask, pl_precision prec, pl_c64* coh,
+                                pl_stream stream) {
+    Geometry g;
+    PL_CHECK(stack && mask && coh, PL_ERR_INVALID_ARG, "pl_estimate_coherence: NULL pointer");
+    PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_estimate_coherence: N=%d outside 1..%d", N, kMaxN);
+    PL_CHECK(make_geometry(R, C, w, &g), PL_ERR_SHAPE, "pl_estimate_coherence: bad image size or window");
+    PL_CHECK(g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE, "pl_estimate_coherence: image smaller than one stride");
+    PL_CHECK(prec == PL_PREC_FP32 || prec == PL_PREC_SPLIT_BF16, PL_ERR_INVALID_ARG,
+             "pl_estimate_coherence: unknown precision %d", (int)prec);
+    PlaneTable t = contiguous_planes(stack, N, R * C);
+    return launch_coherence(t, N, g, mask, (int)prec, reinterpret_cast<float2*>(coh), S(stream));
+}
+
+pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
+                        pl_link_method method, pl_c64* phasors, float* lambda, uint8_t* flags,
+                        uint64_t* counters, pl_stream stream) {
+    PL_CHECK(coh && phasors, PL_ERR_INVALID_ARG, "pl_phase_link: NULL pointer");
+    PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_phase_link: N=%d outside 1..%d", N, kMaxN);
+    PL_CHECK(npix >= 0, PL_ERR_SHAPE, "pl_phase_link: negative pixel count");
+    PL_CHECK(ref_idx >= 0 && ref_idx < N, PL_ERR_INVALID_ARG, "pl_phase_link: ref_idx %d outside 0..%d",
+             ref_idx, N - 1);
+    PL_CHECK(method == PL_LINK_EMI || method == PL_LINK_EVD, PL_ERR_INVALID_ARG,
+             "pl_phase_link: unknown method %d", (int)method);
+    if (npix == 0) return PL_OK;
+    return launch_phase_link(reinterpret_cast<const float2*>(coh), N, npix, ref_idx, (int)method,
+                             reinterpret_cast<float2*>(phasors), lambda, flags,
+                             reinterpret_cast<unsigned long long*>(counters), S(stream));
+}
+
+pl_status pl_compress_ministack(const pl_c64* stack, int32_t N, int32_t first_real, int64_t R,
+                                int64_t C, pl_window w, const pl_c64* phasors, pl_c64* kappa,
+                                pl_stream stream) {
+    Geometry g;
+    PL_CHECK(stack && phasors && kappa, PL_ERR_INVALID_ARG, "pl_compress_ministack: NULL pointer");
+    PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_compress_ministack: N=%d outside 1..%d", N, kMaxN);
+    PL_CHECK(first_real >= 0 && first_real < N, PL_ERR_INVALID_ARG,
+             "pl_compress_ministack: first_real %d outside 0..%d", first_real, N - 1);
+    PL_CHECK(make_geometry(R, C, w, &g), PL_ERR_SHAPE, "pl_compress_ministack: bad image size or window");
+    PL_CHECK(g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE, "pl_compress_ministack: image smaller than one stride");
+    PlaneTable t = contiguous_planes(stack, N, R * C);
+    return launch_compress(t, N, first_real, g, reinterpret_cast<const float2*>(phasors),
+                           reinterpret_cast<float2*>(kappa), S(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,418 @@
+// Windowed sample coherence over SHPs (paper eq. sample-coherence) on the
+// matrix cores.
+//
+// For one output pixel let r_m(k), i_m(k) be the real and imaginary parts of
+// image m at its k-th window sample and s(k) in {0,1} its SHP bit.  Then
+//   Re A = sum_k s (r r^T + i i^T),  Im A = S^T - S,  S = sum_k s r i^T,
+// three real Gram-type products X diag(s) Y^T whose rows are the images
+// (at most 16 or 32) and whose reduction runs over window samples - exactly
+// the operand shape of an MFMA, with A- and B-fragments read by the same
+// lane.  The SHP weight is applied by zeroing masked samples of the A operand
+// only.
+//
+// Plain FP32: v_mfma_f32_{16x16x4,32x32x2}f32 on r, i directly.
+// Split BF16: each value x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+// (about 16 significant bits).  Products hi*hi + hi*lo + lo*hi are kept, lo*lo
+// dropped:  Re A = Whh + Whl + Whl^T  with Whl = sum s (r_h r_l^T + i_h i_l^T),
+// S = V1 + V2^T with V1 = sum s r_h (i_h + i_l)^T, V2 = sum s i_h r_l^T, so
+// Im A = U - U^T with U = V2 - V1;  seven v_mfma_f32_{16x16x32,32x32x16}_bf16
+// per k-step.
+//
+// Data movement: a workgroup owns a strip of TXo output columns and walks
+// down a band of output rows.  The window rows it needs live in an LDS ring
+// of (2*half_y+1) input rows, planar per (component, image) so that the 16
+// or 32 lanes of one fragment read 16 or 32 different planes at one offset
+// (plane strides are odd in 32-bit words: no bank conflicts).  Moving to the
+// next output row loads only the stride_y new input rows.  Every window is
+// cut into pairs of horizontally adjacent pixels starting at an even column,
+// so one 32-bit LDS read yields two BF16 samples; per pixel a wavefront first
+// lists the pairs that hold at least one SHP (LDS offset + 2 SHP bits), then
+// runs the MFMA loop over that compacted list.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace plk {
+namespace {
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMaxWaves = 8;
+
+struct CohArgs {
+    PlaneTable t;
+    int N;
+    Geometry g;
+    const uint32_t* mask;
+    float2* coh;
+    int TXo;          // output columns per strip
+    int rows_per_wg;  // output rows per workgroup
+    int tile_w;       // staged input columns
+    int pitch;        // LDS elements per staged row
+    int plane;        // LDS elements per plane
+    int wave_words;   // 32-bit words of LDS per wavefront
+    int n_pairs;      // pairs per window = (2 hy + 1)(hx + 1)
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return u >> 16;
+}
+
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0)); }
+
+template <int NT>
+struct Acc;
+template <>
+struct Acc<16> {
+    typedef f32x4 T;
+    static constexpr int R = 4;
+    // row index of register v for this lane (column is lane % 16)
+    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <>
+struct Acc<32> {
+    typedef f32x16 T;
+    static constexpr int R = 16;
+    __device__ static int row(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+};
+
+// Stage input row y of the strip into ring slot y mod wy.
+template <bool SPLIT>
+__device__ void load_row(const CohArgs& a, void* lds, int64_t y, int64_t x0, int nthreads) {
+    const Geometry& g = a.g;
+    const int slot = (int)(((y % g.wy) + g.wy) % g.wy);
+    const bool yin = y >= 0 && y < g.R;
+    const int total = a.N * a.tile_w;
+    for (int idx = threadIdx.x; idx < total; idx += nthreads) {
+        const int d = idx / a.tile_w, lx = idx - d * a.tile_w;
+        const int64_t x = x0 + lx;
+        float2 z = make_float2(0.f, 0.f);
+        if (yin && x >= 0 && x < g.C) z = a.t.p[d][y * g.C + x];
+        const int e = slot * a.pitch + lx;
+        if constexpr (SPLIT) {
+            uint16_t* L = reinterpret_cast<uint16_t*>(lds);
+            uint32_t rh = bf16_bits(z.x), ih = bf16_bits(z.y);
+            uint32_t rl = bf16_bits(z.x - bf16_value(rh)), il = bf16_bits(z.y - bf16_value(ih));
+            L[(0 * a.N + d) * a.plane + e] = (uint16_t)rh;
+            L[(1 * a.N + d) * a.plane + e] = (uint16_t)rl;
+            L[(2 * a.N + d) * a.plane + e] = (uint16_t)ih;
+            L[(3 * a.N + d) * a.plane + e] = (uint16_t)il;
+        } else {
+            float* L = reinterpret_cast<float*>(lds);
+            L[(0 * a.N + d) * a.plane + e] = z.x;
+            L[(1 * a.N + d) * a.plane + e] = z.y;
+        }
+    }
+}
+
+// List the window pairs of output pixel (oy, ox) that hold an SHP.  Entry =
+// (element offset << 2) | (bit0 | bit1 << 1), padded with zero entries to a
+// multiple of `ppk`.  Returns the padded count (uniform over the wave).
+__device__ int build_pairs(const CohArgs& a, uint32_t* table, int64_t oy, int64_t ox, int64_t x0,
+                           int ppk, int lane) {
+    const Geometry& g = a.g;
+    const int64_t cy = oy * g.sy + g.sy / 2, cx = ox * g.sx + g.sx / 2;
+    const int rel = (int)(cx - g.hx - x0);  // >= 0 by construction of x0
+    const int xs = rel & ~1, par = rel & 1;
+    const int ppr = g.hx + 1;  // pairs per window row
+    const uint32_t* m = a.mask + (oy * g.oC + ox) * g.nw;
+    int n = 0;
+    for (int base = 0; base < a.n_pairs; base += 64) {
+        const int j = base + lane;
+        uint32_t entry = 0;
+        bool keep = false;
+        if (j < a.n_pairs) {
+            const int dy = j / ppr, px = j - dy * ppr;
+            const int64_t y = cy - g.hy + dy;
+            const int slot = (int)(((y % g.wy) + g.wy) % g.wy);
+            const int dx0 = 2 * px - par, dx1 = dx0 + 1;
+            uint32_t bits = 0;
+            if (dx0 >= 0) {
+                const int b = dy * g.wx + dx0;
+                bits |= (m[b >> 5] >> (b & 31)) & 1u;
+            }
+            if (dx1 <= 2 * g.hx) {
+                const int b = dy * g.wx + dx1;
+                bits |= ((m[b >> 5] >> (b & 31)) & 1u) << 1;
+            }
+            keep = bits != 0;
+            entry = ((uint32_t)(slot * a.pitch + xs + 2 * px) << 2) | bits;
+        }
+        const uint64_t bal = __ballot(keep);
+        const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+        if (keep) table[n + before] = entry;
+        n += __popcll(bal);
+    }
+    const int npad = (n + ppk - 1) / ppk * ppk;
+    for (int j = n + lane; j < npad; j += 64) table[j] = 0u;
+    return npad;
+}
+
+template <int NT>
+__device__ __forceinline__ void transpose_read(float* S, const typename Acc<NT>::T& x,
+                                               typename Acc<NT>::T& xt, int lane) {
+    constexpr int LD = NT + 1;
+    const int j = lane & (NT - 1);
+#pragma unroll
+    for (int v = 0; v < Acc<NT>::R; ++v) S[Acc<NT>::row(lane, v) * LD + j] = x[v];
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < Acc<NT>::R; ++v) xt[v] = S[j * LD + Acc<NT>::row(lane, v)];
+    wave_sync();
+}
+
+// Normalise and store one pixel's matrix from Re/Im in accumulator layout.
+template <int NT>
+__device__ void store_pixel(const CohArgs& a, float* S, const typename Acc<NT>::T& re,
+                            const typename Acc<NT>::T& im, int64_t pix, int lane) {
+    constexpr int LD = NT + 1;
+    float* diag = S + NT * LD;
+    const int j = lane & (NT - 1);
+    const int N = a.N;
+#pragma unroll
+    for (int v = 0; v < Acc<NT>::R; ++v)
+        if (Acc<NT>::row(lane, v) == j) diag[j] = re[v];
+    wave_sync();
+    const float dj = diag[j];
+    const bool bad = (j < N) && !(dj > 0.f && dj <= 3.4e38f);
+    const bool invalid = __ballot(bad) != 0;
+    const float isj = 1.0f / sqrtf(dj);
+    float2* out = a.coh + pix * (int64_t)N * N;
+#pragma unroll
+    for (int v = 0; v < Acc<NT>::R; ++v) {
+        const int i = Acc<NT>::row(lane, v);
+        if (i < N && j < N) {
+            const float isi = 1.0f / sqrtf(diag[i]);
+            float2 c = make_float2(re[v] * isi * isj, im[v] * isi * isj);
+            if (i == j) c = make_float2(1.f, 0.f);
+            if (invalid) c = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+            out[i * N + j] = c;
+        }
+    }
+    wave_sync();
+}
+
+template <int NT, bool SPLIT>
+__device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* table, int npad,
+                           int lane, typename Acc<NT>::T& re, typename Acc<NT>::T& im, float* S) {
+    typedef typename Acc<NT>::T AT;
+    const int d = lane & (NT - 1);
+    const bool live = d < a.N;
+    const int g = lane / NT;  // k-group of this lane
+    AT whh = {}, v1 = {};
+    if constexpr (SPLIT) {
+        AT whl = {}, v2 = {};
+        constexpr int PPK = NT == 16 ? 16 : 8;  // pairs per k-step
+        const uint32_t* L = reinterpret_cast<const uint32_t*>(lds);
+        const int half_plane = a.plane >> 1;  // plane stride in 32-bit words
+        const uint32_t* prh = L + (0 * a.N + d) * half_plane;
+        const uint32_t* prl = L + (1 * a.N + d) * half_plane;
+        const uint32_t* pih = L + (2 * a.N + d) * half_plane;
+        const uint32_t* pil = L + (3 * a.N + d) * half_plane;
+        for (int ks = 0; ks < npad; ks += PPK) {
+            const u32x4 e = *reinterpret_cast<const u32x4*>(table + ks + 4 * g);
+            u32x4 rh, rl, ih, il, rhm, ihm;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t off = e[t] >> 3;  // element offset / 2 = word offset
+                const uint32_t bits = e[t] & 3u;
+                const uint32_t msk = ((bits & 1u) ? 0x0000ffffu : 0u) | ((bits & 2u) ? 0xffff0000u : 0u);
+                uint32_t xrh = 0, xrl = 0, xih = 0, xil = 0;
+                if (live) {
+                    xrh = prh[off];
+                    xrl = prl[off];
+                    xih = pih[off];
+                    xil = pil[off];
+                }
+                rh[t] = xrh;
+                rl[t] = xrl;
+                ih[t] = xih;
+                il[t] = xil;
+                rhm[t] = xrh & msk;
+                ihm[t] = xih & msk;
+            }
+            const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh), Rl = __builtin_bit_cast(bf16x8, rl);
+            const bf16x8 Ih = __builtin_bit_cast(bf16x8, ih), Il = __builtin_bit_cast(bf16x8, il);
+            const bf16x8 Rm = __builtin_bit_cast(bf16x8, rhm), Im = __builtin_bit_cast(bf16x8, ihm);
+            if constexpr (NT == 16) {
+                whh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Rh, whh, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Ih, whh, 0, 0, 0);
+                whl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Rl, whl, 0, 0, 0);
+                whl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Il, whl, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Ih, v1, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Il, v1, 0, 0, 0);
+                v2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Rl, v2, 0, 0, 0);
+            } else {
+                whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Rh, whh, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Ih, whh, 0, 0, 0);
+                whl = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Rl, whl, 0, 0, 0);
+                whl = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Il, whl, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Ih, v1, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Il, v1, 0, 0, 0);
+                v2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Rl, v2, 0, 0, 0);
+            }
+        }
+        AT t;
+        transpose_read<NT>(S, whl, t, lane);
+        re = whh + whl + t;
+        const AT u = v2 - v1;
+        transpose_read<NT>(S, u, t, lane);
+        im = u - t;
+    } else {
+        constexpr int SPK = NT == 16 ? 4 : 2;  // samples per k-step
+        const float* L = reinterpret_cast<const float*>(lds);
+        const float* pr = L + (0 * a.N + d) * a.plane;
+        const float* pi = L + (1 * a.N + d) * a.plane;
+        const int half = g & 1;
+        const int eoff = g >> 1;  // which pair of the k-step (16x16x4 only)
+        for (int ks = 0; ks < npad; ks += SPK / 2) {
+            const uint32_t e = table[ks + eoff];
+            const uint32_t off = (e >> 2) + half;
+            const bool on = (e >> half) & 1u;
+            float r = 0.f, im_ = 0.f;
+            if (live) {
+                r = pr[off];
+                im_ = pi[off];
+            }
+            const float rm = on ? r : 0.f, imm = on ? im_ : 0.f;
+            if constexpr (NT == 16) {
+                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, r, whh, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(imm, im_, whh, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, im_, v1, 0, 0, 0);
+            } else {
+                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, r, whh, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(imm, im_, whh, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, im_, v1, 0, 0, 0);
+            }
+        }
+        re = whh;
+        AT t;
+        transpose_read<NT>(S, v1, t, lane);
+        im = t - v1;
+    }
+}
+
+template <int NT, bool SPLIT>
+__global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
+    const Geometry& g = a.g;
+    const int nthreads = blockDim.x;
+    const int nwaves = nthreads >> 6;
+    const int wave = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t strip = blockIdx.x;
+    const int64_t ox0 = strip * a.TXo;
+    const int64_t ox1 = ox0 + a.TXo < g.oC ? ox0 + a.TXo : g.oC;
+    const int64_t oy0 = (int64_t)blockIdx.y * a.rows_per_wg;
+    const int64_t oy1 = oy0 + a.rows_per_wg < g.oR ? oy0 + a.rows_per_wg : g.oR;
+    const int64_t x0 = (ox0 * g.sx + g.sx / 2 - g.hx) & ~(int64_t)1;
+    const int data_words = 2 * a.N * a.plane;  // 8 bytes per image per element
+    uint32_t* wave_area = lds_words + data_words + wave * a.wave_words;
+    float* S = reinterpret_cast<float*>(wave_area);
+    constexpr int PPK = SPLIT ? (NT == 16 ? 16 : 8) : (NT == 16 ? 2 : 1);
+
+    int64_t loaded_to = INT64_MIN;  // first input row not yet staged
+    for (int64_t oy = oy0; oy < oy1; ++oy) {
+        const int64_t cy = oy * g.sy + g.sy / 2;
+        int64_t yfirst = cy - g.hy;
+        if (loaded_to > yfirst) yfirst = loaded_to;
+        __syncthreads();
+        for (int64_t y = yfirst; y <= cy + g.hy; ++y) load_row<SPLIT>(a, lds_words, y, x0, nthreads);
+        loaded_to = cy + g.hy + 1;
+        __syncthreads();
+        for (int64_t ox = ox0 + wave; ox < ox1; ox += nwaves) {
+            const int npad = build_pairs(a, wave_area, oy, ox, x0, PPK, lane);
+            wave_sync();
+            typename Acc<NT>::T re, im;
+            pixel_gram<NT, SPLIT>(a, lds_words, wave_area, npad, lane, re, im, S);
+            store_pixel<NT>(a, S, re, im, oy * g.oC + ox, lane);
+        }
+    }
+}
+
+template <int NT, bool SPLIT>
+pl_status launch_variant(const CohArgs& a0, hipStream_t s) {
+    CohArgs a = a0;
+    const Geometry& g = a.g;
+    const size_t lds_cap = max_lds_bytes();
+    constexpr int PPK = SPLIT ? (NT == 16 ? 16 : 8) : (NT == 16 ? 2 : 1);
+    const int scratch_words = NT * (NT + 1) + NT;
+    const int table_words = ((a.n_pairs + PPK + 3) / 4) * 4;
+    a.wave_words = ((scratch_words > table_words ? scratch_words : table_words) + 3) / 4 * 4;
+    int chosen = 0;
+    size_t lds = 0;
+    for (int txo = 16; txo >= 1; --txo) {
+        int tile_w = (txo - 1) * g.sx + 2 * g.hx + 3;
+        tile_w += tile_w & 1;
+        int pitch = tile_w;
+        int plane = g.wy * pitch;
+        if (SPLIT) {
+            if (((plane >> 1) & 1) == 0) plane += 2;  // odd word stride between planes
+        } else {
+            if ((plane & 1) == 0) plane += 1;
+        }
+        int nw = txo < kMaxWaves ? txo : kMaxWaves;
+        size_t bytes = (size_t)8 * a.N * plane + (size_t)nw * a.wave_words * 4;
+        if (bytes <= lds_cap) {
+            chosen = txo;
+            a.tile_w = tile_w;
+            a.pitch = pitch;
+            a.plane = plane;
+            lds = bytes;
+            break;
+        }
+    }
+    if (!chosen) return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: window too large for LDS");
+    a.TXo = chosen;
+    const int nwaves = chosen < kMaxWaves ? chosen : kMaxWaves;
+    const int64_t n_strips = (g.oC + chosen - 1) / chosen;
+    // enough workgroups to fill the chip several times over
+    int64_t rows = (g.oR * n_strips + 2047) / 2048;
+    if (rows < 4) rows = 4;
+    if (rows > g.oR) rows = g.oR;
+    a.rows_per_wg = (int)rows;
+    const int64_t n_bands = (g.oR + rows - 1) / rows;
+    if (n_strips > 2147483647LL || n_bands > 65535)
+        return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: output grid too large");
+    auto kern = coherence_kernel<NT, SPLIT>;
+    if (lds > 65536) {
+        pl_status st = hip_ok(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                              "coherence kernel LDS attribute");
+        if (st != PL_OK) return st;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
+    return launch_ok("coherence kernel");
+}
+
+}  // namespace
+
+pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
+                           int prec, float2* coh, hipStream_t s) {
+    CohArgs a{};
+    a.t = t;
+    a.N = N;
+    a.g = g;
+    a.mask = mask;
+    a.coh = coh;
+    a.n_pairs = g.wy * (g.hx + 1);
+    const bool split = prec == PL_PREC_SPLIT_BF16;
+    if (N <= 16) return split ? launch_variant<16, true>(a, s) : launch_variant<16, false>(a, s);
+    return split ? launch_variant<32, true>(a, s) : launch_variant<32, false>(a, s);
+}
+
+}  // namespace plk

@@ -1,0 +1,151 @@
+// GLRT selection of statistically homogeneous pixels (paper Sec. 3.1).
+//
+// A workgroup owns a tile of TX x TY output pixels and stages the Rayleigh
+// scale s = (mean^2 + var)/2 of the input pixels its windows cover in LDS
+// (FP64; NaN outside the image or where s is not finite and positive).  One
+// thread per output pixel walks its window in the mask's bit order.
+//
+// With n samples, T = 2n ln((s_p+s_q)^2 / (4 s_p s_q)) <= thr holds exactly
+// when r = s_q/s_p lies in [1/r_hi, r_hi], r_hi = 2c-1 + 2 sqrt(c^2-c),
+// c = exp(thr/2n), so almost every pair costs two FP64 multiplies and
+// compares.  Pairs whose scale lies within 1e-8 (relative) of either bound
+// are re-decided with the logarithmic form itself, and those with
+// |T - thr| < 1e-9 are counted.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace plk {
+namespace {
+
+constexpr double kRecheckRel = 1e-8;
+constexpr double kBand = 1e-9;
+
+struct GlrtArgs {
+    const double* mean;
+    const double* var;
+    Geometry g;
+    int TX, TY, tw, th;
+    double n, thr, rlo, rhi;
+    uint32_t* mask;
+    uint16_t* count;
+    unsigned long long* counters;
+};
+
+__global__ __launch_bounds__(256) void glrt_kernel(GlrtArgs a) {
+    extern __shared__ double s_tile[];
+    const Geometry& g = a.g;
+    const int64_t oy0 = (int64_t)blockIdx.y * a.TY, ox0 = (int64_t)blockIdx.x * a.TX;
+    const int64_t y0 = oy0 * g.sy + g.sy / 2 - g.hy;
+    const int64_t x0 = ox0 * g.sx + g.sx / 2 - g.hx;
+    const int nt = a.tw * a.th;
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
+        int ly = i / a.tw, lx = i - ly * a.tw;
+        int64_t y = y0 + ly, x = x0 + lx;
+        double s = __builtin_nan("");
+        if (y >= 0 && y < g.R && x >= 0 && x < g.C) {
+            int64_t p = y * g.C + x;
+            double m = a.mean[p], v = a.var[p];
+            double sv = 0.5 * fma(m, m, v);
+            if (sv > 0.0 && sv <= 1.7976931348623157e308) s = sv;
+        }
+        s_tile[i] = s;
+    }
+    __syncthreads();
+
+    const int ly = threadIdx.x / a.TX, lx = threadIdx.x - ly * a.TX;
+    const int64_t oy = oy0 + ly, ox = ox0 + lx;
+    if (ly >= a.TY || oy >= g.oR || ox >= g.oC) return;
+    const double* row0 = s_tile + (ly * g.sy) * a.tw + lx * g.sx;
+    const double sp = row0[g.hy * a.tw + g.hx];
+    const bool pvalid = sp == sp;
+    const double lo = a.rlo * sp, hi = a.rhi * sp;
+    const double lo_tol = kRecheckRel * lo, hi_tol = kRecheckRel * hi;
+    const int64_t pix = oy * g.oC + ox;
+    uint32_t* out = a.mask + pix * g.nw;
+    uint32_t word = 0;
+    int bit = 0, wi = 0, cnt = 0;
+    unsigned long long band = 0, rechecks = 0;
+    for (int dy = 0; dy < g.wy; ++dy) {
+        const double* row = row0 + dy * a.tw;
+        for (int dx = 0; dx < g.wx; ++dx) {
+            const double sq = row[dx];
+            bool ok;
+            if (dy == g.hy && dx == g.hx) {
+                ok = true;
+            } else if (!pvalid) {
+                ok = false;
+            } else {
+                ok = (sq >= lo) && (sq <= hi);  // false for NaN
+                if (fabs(sq - hi) <= hi_tol || fabs(sq - lo) <= lo_tol) {
+                    const double t = 2.0 * a.n * (2.0 * log((sp + sq) * 0.5) - log(sp) - log(sq));
+                    ok = t <= a.thr;
+                    ++rechecks;
+                    if (fabs(t - a.thr) < kBand) ++band;
+                }
+            }
+            word |= (uint32_t)ok << bit;
+            cnt += ok;
+            if (++bit == 32) {
+                out[wi++] = word;
+                word = 0;
+                bit = 0;
+            }
+        }
+    }
+    if (bit) out[wi] = word;
+    a.count[pix] = (uint16_t)cnt;
+    if (a.counters && (band | rechecks)) {
+        atomicAdd(a.counters + PL_CNT_GLRT_BAND, band);
+        atomicAdd(a.counters + PL_CNT_GLRT_RECHECK, rechecks);
+    }
+}
+
+// chi-square (1 dof) upper quantile: thr = z^2 with erfc(z / sqrt(2)) = alpha,
+// found by bisection on the monotone erfc in long double.
+double chi2_1_isf(double alpha) {
+    long double lo = 0.0L, hi = 40.0L;
+    for (int i = 0; i < 200; ++i) {  // bisection to full precision
+        long double mid = 0.5L * (lo + hi);
+        if (erfcl(mid / sqrtl(2.0L)) > (long double)alpha) lo = mid; else hi = mid;
+    }
+    long double z = 0.5L * (lo + hi);
+    return (double)(z * z);
+}
+
+}  // namespace
+
+pl_status launch_shp_select(const double* mean, const double* var, const Geometry& g,
+                            double n_eff, double alpha, uint32_t* mask, uint16_t* count,
+                            unsigned long long* counters, hipStream_t s) {
+    GlrtArgs a{};
+    a.mean = mean;
+    a.var = var;
+    a.g = g;
+    a.mask = mask;
+    a.count = count;
+    a.counters = counters;
+    a.n = n_eff;
+    a.thr = chi2_1_isf(alpha);
+    long double c = expl((long double)a.thr / (2.0L * (long double)n_eff));
+    long double rhi = 2.0L * c - 1.0L + 2.0L * sqrtl(c * c - c);
+    a.rhi = (double)rhi;
+    a.rlo = (double)(1.0L / rhi);
+    const size_t budget = 64 * 1024;
+    static const int shapes[][2] = {{16, 16}, {32, 8}, {16, 8}, {8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}, {1, 1}};
+    for (auto& sh : shapes) {
+        a.TX = sh[0];
+        a.TY = sh[1];
+        a.tw = (a.TX - 1) * g.sx + g.wx;
+        a.th = (a.TY - 1) * g.sy + g.wy;
+        if ((size_t)a.tw * a.th * sizeof(double) <= budget) break;
+    }
+    size_t lds = (size_t)a.tw * a.th * sizeof(double);
+    if (lds > budget) return fail(PL_ERR_UNSUPPORTED, "pl_shp_select: window/stride too large for LDS");
+    dim3 grid((unsigned)((g.oC + a.TX - 1) / a.TX), (unsigned)((g.oR + a.TY - 1) / a.TY));
+    if (grid.y > 65535) return fail(PL_ERR_UNSUPPORTED, "pl_shp_select: output grid too tall");
+    hipLaunchKernelGGL(glrt_kernel, grid, dim3(a.TX * a.TY), lds, s, a);
+    return launch_ok("GLRT kernel");
+}
+
+}  // namespace plk

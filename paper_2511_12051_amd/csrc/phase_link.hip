@@ -1,0 +1,370 @@
+// EMI phase linking with EVD fallback (paper Sec. 3.2, eq.
+// emi-eigenvalue-problem) and the reference gauge of Sec. 2.1.
+//
+// Layout: a group of NP = 16 or 32 lanes owns one pixel, lane i holds row i of
+// every matrix in registers (NP <= 32 images), so a wavefront solves 4 or 2
+// pixels side by side.  The pivot row of each Gauss-Jordan step and the
+// current iterate are broadcast through a few hundred bytes of LDS per group.
+//
+//  1. G = |C| in FP64; in-place Gauss-Jordan inversion.  Its pivots are the
+//     LDL^T pivots of G; one <= 1e-6 (or not finite) means the inversion
+//     failed and the pixel takes the EVD branch.
+//  2. B = G^{-1} o C (EMI) or B = -C (EVD); both need the eigenvector of the
+//     smallest eigenvalue of the Hermitian B.
+//  3. Shifted inverse iteration with an explicit (B - mu I)^{-1}, formed by
+//     complex Gauss-Jordan in FP32.  All pivots positive proves
+//     mu < lambda_min (Sylvester's inertia), so the iteration converges to the
+//     wanted eigenvector.  EMI starts from mu = 0.99 (Sec. 3.2) and backs off
+//     if the inertia check fails; EVD starts from minus the largest absolute
+//     row sum of C (a Gershgorin bound).  After 3, 6 and 9 iterations the shift
+//     moves up to rho - ||B x - rho x|| (rho the Rayleigh quotient), a bound
+//     that lies below the eigenvalue nearest rho, again accepted only if the
+//     inertia check passes; this keeps the iteration count low when the
+//     eigen-gap is small compared with the distance from 0.99.
+//  4. zeta_i = x_i conj(x_ref), returned as unit phasors.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace plk {
+namespace {
+
+constexpr double kTauPivot = 1e-6;
+constexpr float kTol2 = 4e-12f;  // squared change of the unit iterate at convergence
+constexpr int kMaxIter = 48;
+constexpr int kBlock = 256;
+
+struct LinkArgs {
+    const float2* coh;
+    int N;
+    int64_t npix;
+    int ref;
+    int method;
+    float2* ph;
+    float* lam;
+    uint8_t* flags;
+    unsigned long long* counters;
+};
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
+}
+
+template <int NP>
+__device__ __forceinline__ float gsum(float v) {
+#pragma unroll
+    for (int o = NP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NP>
+__device__ __forceinline__ float gmax(float v) {
+#pragma unroll
+    for (int o = NP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int NP>
+__device__ __forceinline__ bool gany(bool p, int grp) {
+    const uint64_t b = __ballot(p);
+    const uint64_t m = (NP == 64 ? ~0ull : ((1ull << NP) - 1)) << (grp * NP);
+    return (b & m) != 0;
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-place complex Gauss-Jordan inversion of the Hermitian matrix (m - mu I),
+// row i of m being this lane's m[].  Lanes with act == false keep m unchanged.  Returns
+// (per group) whether every pivot was positive and finite.
+// The shift mu is subtracted from each diagonal entry when its row becomes
+// the pivot: earlier steps only add multiples of pivot rows to it, so this is
+// the same as shifting the matrix first.
+template <int NP>
+__device__ bool invert_c(float2 (&m)[NP], float mu, int N, int i, bool act, float2* rb) {
+    bool pd = true;
+#pragma unroll NP
+    for (int k = 0; k < NP; ++k) {
+        if (k < N) {
+            if (i == k && act) {
+                const float p = m[k].x - mu;
+                const float inv = 1.0f / p;
+#pragma unroll
+                for (int j = 0; j < NP; ++j) m[j] = make_float2(m[j].x * inv, m[j].y * inv);
+                m[k] = make_float2(inv, 0.f);
+#pragma unroll
+                for (int j = 0; j < NP; ++j) rb[j] = m[j];
+                rb[NP] = make_float2(p, 0.f);
+            }
+            wave_sync();
+            if (act) {
+                const float p = rb[NP].x;
+                pd = pd && (p > 0.f) && (p <= 3.4e38f);
+                if (i != k) {
+                    const float2 f = m[k];
+                    m[k] = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) {
+                        const float2 r = rb[j];
+                        m[j].x = fmaf(-f.x, r.x, fmaf(f.y, r.y, m[j].x));
+                        m[j].y = fmaf(-f.x, r.y, fmaf(-f.y, r.x, m[j].y));
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+    return pd;
+}
+
+template <int NP>
+__device__ __forceinline__ float2 matvec(const float2 (&m)[NP], float2 x, int i, float2* xb) {
+    xb[i] = x;
+    wave_sync();
+    float2 y = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const float2 v = xb[j];
+        y.x = fmaf(m[j].x, v.x, fmaf(-m[j].y, v.y, y.x));
+        y.y = fmaf(m[j].x, v.y, fmaf(m[j].y, v.x, y.y));
+    }
+    wave_sync();
+    return y;
+}
+
+template <int NP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, NP == 16 ? 4 : 2)))
+void phase_link_kernel(LinkArgs a) {
+    constexpr int GPW = 64 / NP;  // groups (pixels) per wavefront
+    // per group: GJ row buffer (NP + 2 doubles) and iterate buffer (NP float2)
+    constexpr int GROUP_BYTES = (NP + 2) * 8 + NP * 8;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[(kBlock / 64) * GPW * GROUP_BYTES];
+    const int lane = lane_id();
+    const int i = lane & (NP - 1);
+    const int grp = lane / NP;
+    const int wave = threadIdx.x >> 6;
+    unsigned char* gbase = lds + (wave * GPW + grp) * GROUP_BYTES;
+    double* rbd = reinterpret_cast<double*>(gbase);
+    float2* rbc = reinterpret_cast<float2*>(gbase);
+    float2* xb = reinterpret_cast<float2*>(gbase + (NP + 2) * 8);
+
+    const int N = a.N;
+    const int64_t pix = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * GPW + grp;
+    const bool active = pix < a.npix;
+    const bool row_live = active && i < N;
+
+    // ---- load row i of C
+    float2 c[NP];
+    const float2* src = a.coh + (active ? pix : 0) * (int64_t)N * N + (int64_t)i * N;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
+    const bool invalid = !active || gany<NP>(bad, grp);
+
+    // start from column ref of C: the single-reference interferogram phases
+    float2 x = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+        if (j == a.ref && row_live) x = c[j];
+    {
+        float nrm = gsum<NP>(x.x * x.x + x.y * x.y);
+        if (!(nrm > 0.f)) {
+            x = make_float2(i == a.ref ? 1.f : 0.f, 0.f);
+            nrm = 1.f;
+        }
+        const float s = 1.0f / sqrtf(nrm);
+        x.x *= s;
+        x.y *= s;
+    }
+    // EVD shift: minus a Gershgorin bound on lambda_max(C), so -C - mu I > 0
+    float evd_shift;
+    {
+        float rs = 0.f;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) rs += sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
+        evd_shift = -(1.0f + 1e-3f) * gmax<NP>(rs) - 1e-3f;
+    }
+
+    // ---- 1. FP64 inverse of G = |C|
+    bool use_evd = a.method == PL_LINK_EVD;
+    double gi[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const double re = c[j].x, im = c[j].y;
+        gi[j] = (row_live && j < N) ? sqrt(fma(re, re, im * im)) : 0.0;
+    }
+    const bool do_emi = !use_evd && !invalid;
+    bool gfail = false;
+    if (gany<64>(do_emi, 0)) {
+#pragma unroll NP
+        for (int k = 0; k < NP; ++k) {
+            if (k < N) {
+                if (i == k && do_emi) {
+                    const double p = gi[k];
+                    const double inv = 1.0 / p;
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) gi[j] *= inv;
+                    gi[k] = inv;
+#pragma unroll
+                    for (int j = 0; j < NP; ++j) rbd[j] = gi[j];
+                    rbd[NP] = p;
+                }
+                wave_sync();
+                if (do_emi) {
+                    const double p = rbd[NP];
+                    gfail = gfail || !(p > kTauPivot && p <= 1.7976931348623157e308);
+                    if (i != k) {
+                        const double f = gi[k];
+                        gi[k] = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NP; ++j) gi[j] = fma(-f, rbd[j], gi[j]);
+                    }
+                }
+                wave_sync();
+            }
+        }
+    }
+    use_evd = use_evd || gfail;
+
+    // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted
+    float2 b[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        if (use_evd) b[j] = make_float2(-c[j].x, -c[j].y);
+        else b[j] = make_float2((float)gi[j] * c[j].x, (float)gi[j] * c[j].y);
+    }
+    float mu = use_evd ? evd_shift : 0.99f;
+
+    // ---- 3. shifted inverse iteration.  One factorisation site serves the
+    // first shift, its back-off schedule, the refined shifts and restoring
+    // the previous factorisation when a refined shift fails the inertia check.
+    float2 m[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) m[j] = make_float2(0.f, 0.f);
+    const bool solve = !invalid;
+    float mu_req = mu;           // shift of the pending factorisation
+    bool need = solve;           // this group waits for a factorisation
+    int stage = 0;               // 0..3: first-shift schedule, 4: refining, 5: restoring
+    bool conv = !solve;
+    int it = 0, retries = 0;
+    for (int guard = 0; guard < 4 * kMaxIter; ++guard) {
+        if (gany<64>(need, 0)) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) if (need) m[j] = b[j];
+            const bool ok = invert_c<NP>(m, mu_req, N, i, need, rbc);
+            if (need) {
+                if (ok) {
+                    mu = mu_req;
+                    need = false;
+                    stage = stage < 4 ? stage : 4;
+                } else if (stage == 4) {  // refined shift rejected: factor the old one again
+                    ++retries;
+                    mu_req = mu;
+                    stage = 5;
+                } else if (stage == 5) {  // cannot happen in exact arithmetic; stop here
+                    need = false;
+                    conv = true;
+                } else {  // first shift rejected: back off
+                    ++retries;
+                    ++stage;
+                    if (stage == 1) mu_req = 0.5f;
+                    else if (stage == 2) mu_req = 0.0f;
+                    else if (stage == 3) {
+                        float fr = 0.f;
+#pragma unroll
+                        for (int j = 0; j < NP; ++j) fr += b[j].x * b[j].x + b[j].y * b[j].y;
+                        mu_req = -sqrtf(gsum<NP>(fr)) - 1.0f;  // below -||B||_F <= lambda_min
+                    } else {
+                        need = false;
+                        conv = true;
+                    }
+                }
+            }
+            continue;
+        }
+        if (!gany<64>(!conv, 0) || it >= kMaxIter) break;
+        float2 y = matvec<NP>(m, x, i, xb);
+        const float n2 = gsum<NP>(y.x * y.x + y.y * y.y);
+        const float sc = 1.0f / sqrtf(n2);
+        y.x *= sc;
+        y.y *= sc;
+        const float dx = y.x - x.x, dy = y.y - x.y;
+        const float d2 = gsum<NP>(dx * dx + dy * dy);
+        const bool finite = n2 > 0.f && n2 <= 3.4e38f;
+        if (!conv) {
+            if (finite) x = y;
+            if (d2 < kTol2 || !finite) conv = true;
+        }
+        ++it;
+        if (it == 3 || it == 6 || it == 9) {
+            if (gany<64>(!conv, 0)) {
+                const float2 bx = matvec<NP>(b, x, i, xb);
+                const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
+                const float rx = bx.x - rho * x.x, ry = bx.y - rho * x.y;
+                const float res = sqrtf(gsum<NP>(rx * rx + ry * ry));
+                const float mu2 = rho - res;
+                if (!conv && mu2 > mu) {
+                    mu_req = mu2;
+                    need = true;
+                    stage = 4;
+                }
+            }
+        }
+    }
+
+    // ---- 4. eigenvalue, reference and unit phasors
+    const float2 bx = matvec<NP>(b, x, i, xb);
+    const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
+    const float2 xr = make_float2(__shfl(x.x, grp * NP + a.ref, 64), __shfl(x.y, grp * NP + a.ref, 64));
+    float2 z = make_float2(x.x * xr.x + x.y * xr.y, x.y * xr.x - x.x * xr.y);  // x conj(x_ref)
+    const float zn = sqrtf(z.x * z.x + z.y * z.y);
+    float2 phv = (zn > 0.f && !invalid) ? make_float2(z.x / zn, z.y / zn) : make_float2(1.f, 0.f);
+    if (i == a.ref) phv = make_float2(1.f, 0.f);
+    if (row_live) a.ph[(int64_t)i * a.npix + pix] = phv;
+    const uint8_t flag = invalid ? PL_FLAG_INVALID : (use_evd ? PL_FLAG_EVD : PL_FLAG_EMI);
+    if (active && i == 0) {
+        if (a.lam) a.lam[pix] = invalid ? __builtin_nanf("") : (use_evd ? -rho : rho);
+        if (a.flags) a.flags[pix] = flag;
+    }
+    if (a.counters) {
+        const bool lead = active && i == 0;
+        const uint64_t e = __ballot(lead && flag == PL_FLAG_EVD);
+        const uint64_t v = __ballot(lead && flag == PL_FLAG_INVALID);
+        const uint64_t nc = __ballot(lead && !conv);
+        const int rt = (int)gsum<64>(lead ? (float)retries : 0.f);
+        const int its = (int)gsum<64>(lead ? (float)it : 0.f);
+        if (lane == 0) {
+            if (e) atomicAdd(a.counters + PL_CNT_EVD, (unsigned long long)__popcll(e));
+            if (v) atomicAdd(a.counters + PL_CNT_INVALID, (unsigned long long)__popcll(v));
+            if (nc) atomicAdd(a.counters + PL_CNT_NOT_CONVERGED, (unsigned long long)__popcll(nc));
+            if (rt) atomicAdd(a.counters + PL_CNT_SHIFT_RETRY, (unsigned long long)rt);
+            if (its) atomicAdd(a.counters + PL_CNT_ITERS, (unsigned long long)its);
+        }
+    }
+}
+
+}  // namespace
+
+pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int method,
+                            float2* phasors, float* lambda, uint8_t* flags,
+                            unsigned long long* counters, hipStream_t s) {
+    LinkArgs a{coh, N, npix, ref, method, phasors, lambda, flags, counters};
+    const int np = N <= 16 ? 16 : 32;
+    const int64_t per_block = (kBlock / 64) * (64 / np);
+    const int64_t blocks = (npix + per_block - 1) / per_block;
+    if (blocks > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link: too many pixels");
+    if (np == 16) hipLaunchKernelGGL(phase_link_kernel<16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(phase_link_kernel<32>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    return launch_ok("phase linking kernel");
+}
+
+}  // namespace plk

@@ -1,0 +1,129 @@
+// Amplitude statistics and their pooled merge (paper Sec. 3.1,
+// eq. merged-mean and eq. merged-variance).  HBM-bound streaming kernels:
+// one thread per two adjacent pixels, 16-byte loads, FP64 accumulation.
+#include "internal.hpp"
+
+namespace plk {
+namespace {
+
+constexpr int kBlock = 256;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Shifted single-pass moments: with K the first amplitude of the pixel,
+// s = sum(a - K), q = sum((a - K)^2) give mean = K + s/M and the population
+// variance (q - s^2/M)/M without the cancellation of sum(a^2) - M mean^2.
+struct Moments {
+    double k = 0, s = 0, q = 0;
+    __device__ void add(double a, int m) {
+        if (m == 0) k = a;
+        double d = a - k;
+        s += d;
+        q = fma(d, d, q);
+    }
+    __device__ void finish(int M, double* mean, double* var) const {
+        double inv = 1.0 / (double)M;
+        *mean = k + s * inv;
+        double v = (q - s * s * inv) * inv;
+        *var = v > 0.0 ? v : 0.0;
+    }
+};
+
+__device__ inline double amp(float re, float im) {
+    double r = re, i = im;
+    return sqrt(fma(r, r, i * i));
+}
+
+// 16-byte aligned planes with an even pixel count: one float4 = two pixels.
+__global__ __launch_bounds__(kBlock) void amp_stats_vec(PlaneTable t, int first, int M,
+                                                        int64_t npair, double* __restrict__ mean,
+                                                        double* __restrict__ var) {
+    int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= npair) return;
+    Moments a, b;
+    for (int m = 0; m < M; ++m) {
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(t.p[first + m]) + j);
+        a.add(amp(v.x, v.y), m);
+        b.add(amp(v.z, v.w), m);
+    }
+    double m0, v0, m1, v1;
+    a.finish(M, &m0, &v0);
+    b.finish(M, &m1, &v1);
+    reinterpret_cast<double2*>(mean)[j] = make_double2(m0, m1);
+    reinterpret_cast<double2*>(var)[j] = make_double2(v0, v1);
+}
+
+__global__ __launch_bounds__(kBlock) void amp_stats_scalar(PlaneTable t, int first, int M,
+                                                           int64_t npix, double* __restrict__ mean,
+                                                           double* __restrict__ var) {
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= npix) return;
+    Moments a;
+    for (int m = 0; m < M; ++m) {
+        float2 v = t.p[first + m][p];
+        a.add(amp(v.x, v.y), m);
+    }
+    a.finish(M, mean + p, var + p);
+}
+
+struct GroupTable {
+    const double* mean[64];
+    const double* var[64];
+    double w[64];
+};
+
+__global__ __launch_bounds__(kBlock) void merge_stats_kernel(GroupTable g, int G, double wsum_inv,
+                                                             int64_t npix, double* mean_out,
+                                                             double* var_out) {
+    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= npix) return;
+    double mu = 0.0, second = 0.0;
+    for (int i = 0; i < G; ++i) {
+        double m = g.mean[i][p], v = g.var[i][p];
+        mu = fma(g.w[i], m, mu);
+        second = fma(g.w[i], fma(m, m, v), second);
+    }
+    mu *= wsum_inv;
+    second *= wsum_inv;
+    mean_out[p] = mu;
+    var_out[p] = second - mu * mu;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+pl_status launch_amp_stats(const PlaneTable& t, int first, int M, int64_t npix, double* mean,
+                           double* var, hipStream_t s) {
+    bool vec = (npix % 2 == 0) && aligned16(mean) && aligned16(var);
+    for (int m = 0; m < M && vec; ++m) vec = aligned16(t.p[first + m]);
+    if (vec) {
+        int64_t npair = npix / 2;
+        int64_t blocks = (npair + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(amp_stats_vec, dim3((unsigned)blocks), dim3(kBlock), 0, s, t, first, M,
+                           npair, mean, var);
+    } else {
+        int64_t blocks = (npix + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(amp_stats_scalar, dim3((unsigned)blocks), dim3(kBlock), 0, s, t, first,
+                           M, npix, mean, var);
+    }
+    return launch_ok("amplitude statistics kernel");
+}
+
+pl_status launch_merge_stats(const double* const* means, const double* const* vars,
+                             const double* weights, int G, int64_t npix, double* mean_out,
+                             double* var_out, hipStream_t s) {
+    GroupTable g{};
+    double wsum = 0.0;
+    for (int i = 0; i < G; ++i) {
+        g.mean[i] = means[i];
+        g.var[i] = vars[i];
+        g.w[i] = weights[i];
+        wsum += weights[i];
+    }
+    int64_t blocks = (npix + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(merge_stats_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, g, G,
+                       1.0 / wsum, npix, mean_out, var_out);
+    return launch_ok("statistics merge kernel");
+}
+
+}  // namespace plk

@@ -1,0 +1,101 @@
+"""The C ABI library: it loads, exports every symbol the header declares, and
+its host-side checks reject bad arguments before touching a GPU (no compute
+call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2511_12051_amd as plink
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "plink.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pl_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(plink.library_path()):
+        pytest.fail("libplink.so is not built (python -m paper_2511_12051_amd.build)")
+    return plink.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares a signature for each of them
+    assert set(names) == set(plink._SIGNATURES)
+
+
+def test_status_strings_and_version(lib):
+    assert lib.pl_version().decode().startswith("plink")
+    for s in range(7):
+        assert lib.pl_status_string(s).decode()
+    assert lib.pl_status_string(99).decode() == "unknown status"
+
+
+def test_output_grid_and_mask_words():
+    assert plink.output_grid(2048, 8192, (11, 5, 6, 3)) == (682, 1365)
+    assert plink.output_grid(64, 64, (5, 5, 1, 1)) == (64, 64)
+    assert plink.output_grid(10, 14, (2, 1, 4, 3)) == (3, 3)
+    assert plink.mask_words((11, 5, 6, 3)) == 8
+    assert plink.mask_words((19, 9, 6, 3)) == 24
+    with pytest.raises(plink.PlinkError):
+        plink.mask_words((16, 16, 1, 1))  # 33 x 33 = 1089 > PL_MAX_WINDOW
+    with pytest.raises(plink.PlinkError):
+        plink.output_grid(0, 5, (1, 1, 1, 1))
+
+
+def _w(*v):
+    return plink._Window(*v)
+
+
+def test_argument_errors_return_before_any_device_work(lib):
+    P = ctypes.c_void_p
+    fake = P(0x1000)  # never dereferenced: every call below fails its checks first
+    # NULL pointers
+    assert lib.pl_amplitude_stats(None, 5, 4, 4, fake, fake, None) == 1
+    assert lib.pl_shp_select(fake, fake, 8, 8, 10.0, _w(1, 1, 1, 1), 1e-3, None, fake, None, None) == 1
+    # N outside 1..32
+    assert lib.pl_estimate_coherence(fake, 33, 8, 8, _w(1, 1, 1, 1), fake, 0, fake, None) == 3
+    assert lib.pl_phase_link(fake, 0, 10, 0, 0, fake, None, None, None, None) == 3
+    assert lib.pl_amplitude_stats(fake, 40, 4, 4, fake, fake, None) == 3
+    # bad window / shapes
+    assert lib.pl_shp_select(fake, fake, 8, 8, 10.0, _w(-1, 1, 1, 1), 1e-3, fake, fake, None, None) == 2
+    assert lib.pl_shp_select(fake, fake, 2, 2, 10.0, _w(1, 1, 3, 3), 1e-3, fake, fake, None, None) == 2
+    # bad scalars
+    assert lib.pl_shp_select(fake, fake, 8, 8, 0.0, _w(1, 1, 1, 1), 1e-3, fake, fake, None, None) == 1
+    assert lib.pl_shp_select(fake, fake, 8, 8, 5.0, _w(1, 1, 1, 1), 1.5, fake, fake, None, None) == 1
+    assert lib.pl_phase_link(fake, 5, 10, 5, 0, fake, None, None, None, None) == 1
+    assert lib.pl_phase_link(fake, 5, 10, 0, 7, fake, None, None, None, None) == 1
+    assert lib.pl_estimate_coherence(fake, 5, 8, 8, _w(1, 1, 1, 1), fake, 9, fake, None) == 1
+    assert lib.pl_compress_ministack(fake, 5, 5, 8, 8, _w(1, 1, 1, 1), fake, fake, None) == 1
+    w = (ctypes.c_double * 2)(1.0, -1.0)
+    assert lib.pl_merge_amplitude_stats(fake, fake, w, 2, 4, 4, fake, fake, None) == 1
+    # empty pixel list is a no-op
+    assert lib.pl_phase_link(fake, 5, 0, 0, 0, fake, None, None, None, None) == 0
+    assert "ref_idx" in lib.pl_last_error().decode() or lib.pl_last_error() is not None
+
+
+def test_sequential_parameter_checks(lib):
+    p = plink._SeqParams(64, 64, 20, 13, _w(2, 2, 1, 1), 1e-3, 0, 0)  # M + K_max > 32
+    h = ctypes.c_void_p()
+    assert lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)) == 3
+    p = plink._SeqParams(64, 64, 15, 6, _w(2, 2, 1, 1), 2.0, 0, 0)
+    assert lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)) == 1
+    assert lib.pl_seq_destroy(None) == 0
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    x = torch.zeros((3, 4, 4), dtype=torch.complex64)
+    with pytest.raises(plink.PlinkError):
+        plink.amplitude_stats(x)

@@ -1,0 +1,283 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle, element by
+element, on seeded synthetic stacks that span several tiles with ragged
+edges, plus edge cases.
+
+Tolerances (from the workload descriptions): SHP masks bit-exact except GLRT
+tests within 1e-9 of the threshold; coherence within 1e-4 per element; linked
+phases within 1e-3 rad (wrapped) on well-posed pixels.  A pixel is well-posed
+when the oracle's statistical phase sensitivity (rad per unit change of C)
+times the coherence difference actually present at that pixel (at least
+1e-6, the FP32 floor of the eigen-solver), times a safety factor of 3, stays
+below 1e-3 rad; the others are counted and must be a small minority.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import plink_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+PHASE_TOL = 1e-3
+COH_TOL = 1e-4
+EPS_FLOOR = 1e-6
+SAFETY = 3.0
+
+
+def _wl(name, R=None, C=None):
+    return synth.WORKLOADS[name] if R is None else synth.crop(name, R, C)
+
+
+CASES = {
+    "tiny": dict(wl=("tiny",), seed=11),
+    "burst-crop": dict(wl=("burst", 192, 390), seed=12),   # 64 x 65 outputs: ragged strips
+    "scale-crop": dict(wl=("scale", 99, 384), seed=13),    # N = 25, 33 x 64 outputs
+    "adjoint-crop": dict(wl=("adjoint", 80, 88), seed=14),  # N = 20, stride 1, 15x15 window
+}
+
+
+class Case:
+    def __init__(self, name):
+        spec = CASES[name]
+        self.name = name
+        self.wl = _wl(*spec["wl"])
+        self.seed = spec["seed"]
+        self.stack = synth.make_stack(self.wl, seed=self.seed)  # CPU, complex64
+        self.z = self.stack.numpy()
+        wl = self.wl
+        self.ref = max(0, wl.n_comp - 1)
+        self.first_real = wl.n_comp
+        self.orc = O.link_ministack(self.z, self.first_real, wl.window, wl.alpha, self.ref)
+        _, _, _, self.stat = O.shp_select(self.orc["mean"], self.orc["var"], wl.n_new, wl.window,
+                                          wl.alpha, return_stat=True)
+        self.sens = O.phase_sensitivity(self.orc["coh"], ref=self.ref)
+
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        print(f"[parity] preparing oracle for {name}", flush=True)
+        _cache[name] = Case(name)
+    return _cache[name]
+
+
+def gpu_path(plink, c: Case, prec="fp32"):
+    wl = c.wl
+    z = c.stack.cuda()
+    mean, var = plink.amplitude_stats(z[c.first_real:].contiguous())
+    cnt = plink.new_counters()
+    mask, count = plink.shp_select(mean, var, wl.n_new, wl.window, wl.alpha, counters=cnt)
+    coh = plink.estimate_coherence(z, mask, wl.window, precision=prec)
+    ph, lam, flags = plink.phase_link(coh, ref=c.ref, counters=cnt)
+    oR, oC = wl.out_shape
+    kappa = plink.compress_ministack(z, c.first_real, wl.window, ph.view(wl.N, oR, oC))
+    torch.cuda.synchronize()
+    return dict(mean=mean.cpu().numpy(), var=var.cpu().numpy(),
+                mask=mask.cpu().numpy().view(np.uint32), count=count.cpu().numpy().view(np.uint16),
+                coh=coh.cpu().numpy(), ph=ph.cpu().numpy(), lam=lam.cpu().numpy(),
+                flags=flags.cpu().numpy(), kappa=kappa.cpu().numpy(), counters=cnt.cpu().numpy())
+
+
+def phase_errors(ph_gpu, ph_orc):
+    return np.abs(np.angle(ph_gpu * np.conj(ph_orc)))  # wrapped difference, [N, P]
+
+
+def well_posed(c: Case, coh_gpu):
+    dC = np.abs(coh_gpu.astype(np.complex128) - c.orc["coh"]).reshape(len(c.sens), -1)
+    eps = np.maximum(np.nanmax(np.where(np.isfinite(dC), dC, np.inf), axis=1), EPS_FLOOR)
+    return SAFETY * c.sens * eps <= PHASE_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_amplitude_stats(gpu_lib, name):
+    c = case(name)
+    g = gpu_path(gpu_lib, c)
+    np.testing.assert_allclose(g["mean"], c.orc["mean"], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(g["var"], c.orc["var"], rtol=1e-10, atol=1e-15 * np.max(c.orc["mean"]) ** 2)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_shp_masks_bit_exact(gpu_lib, name):
+    c = case(name)
+    g = gpu_path(gpu_lib, c)
+    wl = c.wl
+    band = np.abs(c.stat - O.glrt_threshold(wl.alpha)) < O.GLRT_BAND  # [oR, oC, W]
+    bg = O.mask_bits(g["mask"], wl.window)
+    bo = O.mask_bits(c.orc["mask"], wl.window)
+    diff = (bg != bo) & ~band
+    print(f"[parity] {name}: band cases {int(band.sum())}, gpu band count {int(g['counters'][0])}")
+    assert not diff.any(), f"{int(diff.sum())} mask bits differ outside the band"
+    np.testing.assert_array_equal(g["count"][~band.any(-1)], c.orc["count"][~band.any(-1)])
+    # padding bits above W stay clear
+    W = bo.shape[-1]
+    if W % 32:
+        assert np.all(g["mask"][..., -1] >> np.uint32(W % 32) == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_coherence(gpu_lib, name, prec):
+    c = case(name)
+    g = gpu_path(gpu_lib, c, prec)
+    # same masks (previous test), so the matrices are comparable pixel by pixel
+    ok = np.all(np.isfinite(c.orc["coh"].reshape(len(c.sens), -1)), axis=1)
+    d = np.abs(g["coh"][ok].astype(np.complex128) - c.orc["coh"][ok])
+    print(f"[parity] {name} {prec}: max |dC| {d.max():.3e}, mean {d.mean():.3e}")
+    assert d.max() <= COH_TOL
+    # Hermitian with an exact unit diagonal
+    gc = g["coh"][ok]
+    assert np.all(gc[:, np.arange(c.wl.N), np.arange(c.wl.N)] == 1)
+    np.testing.assert_allclose(gc, np.conj(np.swapaxes(gc, 1, 2)), atol=2e-6)
+    assert np.all(np.isnan(g["coh"][~ok]))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_phase_link_on_oracle_coherence(gpu_lib, name):
+    """The eigen-solver alone, fed the oracle's matrices rounded to complex64."""
+    c = case(name)
+    P = len(c.sens)
+    C64 = torch.from_numpy(c.orc["coh"].astype(np.complex64)).cuda()
+    cnt = gpu_lib.new_counters()
+    ph, lam, flags = gpu_lib.phase_link(C64, ref=c.ref, counters=cnt)
+    ph, lam, flags = ph.cpu().numpy(), lam.cpu().numpy(), flags.cpu().numpy()
+    link = c.orc["link"]
+    boundary = (link["min_pivot"] > O.TAU_PIVOT / 2) & (link["min_pivot"] < 2 * O.TAU_PIVOT)
+    same = (flags == link["flag"]) | boundary
+    assert same.all(), f"{int((~same).sum())} EMI/EVD decisions differ outside the boundary band"
+    dC = np.abs(c.orc["coh"].astype(np.complex64).astype(np.complex128) - c.orc["coh"]).reshape(P, -1)
+    eps = np.maximum(np.nanmax(np.where(np.isfinite(dC), dC, 0), axis=1), EPS_FLOOR)
+    wp = (SAFETY * c.sens * eps <= PHASE_TOL) & (flags == link["flag"])
+    err = phase_errors(ph, link["phasor"])
+    worst = err[:, wp].max() if wp.any() else 0.0
+    print(f"[parity] {name}: well-posed {wp.mean():.4f}, max err {worst:.2e} rad, "
+          f"p99 all {np.percentile(err, 99):.2e}, counters {cnt.cpu().numpy()[:7]}")
+    assert wp.mean() > 0.9
+    assert worst <= PHASE_TOL
+    assert np.all(ph[c.ref] == 1)
+    # eigenvalue of the returned vector
+    emi = wp & (flags == 0)
+    np.testing.assert_allclose(lam[emi], link["lam"][emi], rtol=1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_end_to_end_phases(gpu_lib, name, prec):
+    c = case(name)
+    g = gpu_path(gpu_lib, c, prec)
+    link = c.orc["link"]
+    wp = well_posed(c, g["coh"]) & (g["flags"] == link["flag"])
+    err = phase_errors(g["ph"], link["phasor"])
+    worst = err[:, wp].max()
+    print(f"[parity] {name} {prec}: well-posed {wp.mean():.4f}, max err {worst:.2e} rad, "
+          f"median all {np.median(err):.2e}")
+    assert wp.mean() > 0.85
+    assert worst <= PHASE_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_compress_on_oracle_phasors(gpu_lib, name):
+    c = case(name)
+    wl = c.wl
+    oR, oC = wl.out_shape
+    ph = torch.from_numpy(c.orc["phasor"].astype(np.complex64)).cuda().contiguous()
+    k = gpu_lib.compress_ministack(c.stack.cuda(), c.first_real, wl.window, ph).cpu().numpy()
+    want = O.compress(c.z, c.first_real, c.orc["phasor"].astype(np.complex64), wl.window)
+    scale = np.abs(c.z[c.first_real:]).astype(np.float64).sum(0)
+    assert np.max(np.abs(k - want) / scale) <= 1e-6
+
+
+def test_merge_amplitude_stats(gpu_lib):
+    rng = np.random.default_rng(21)
+    G, R, C = 5, 37, 53
+    means = rng.uniform(0.1, 3, (G, R, C))
+    var = rng.uniform(0.0, 2, (G, R, C))
+    w = [15, 15, 15, 7, 3]
+    mo, vo = O.merge_amplitude_stats(list(means), list(var), w)
+    mg, vg = gpu_lib.merge_amplitude_stats(torch.from_numpy(means).cuda(), torch.from_numpy(var).cuda(), w)
+    np.testing.assert_allclose(mg.cpu().numpy(), mo, rtol=1e-14)
+    np.testing.assert_allclose(vg.cpu().numpy(), vo, rtol=1e-11, atol=1e-14)
+
+
+# ------------------------------------------------------------------ edge cases
+def test_two_images_closed_form(gpu_lib):
+    rng = np.random.default_rng(22)
+    P = 1000
+    g = rng.uniform(0.05, 0.99, P)
+    th = rng.uniform(-np.pi, np.pi, P)
+    Cm = np.zeros((P, 2, 2), np.complex64)
+    Cm[:, 0, 0] = Cm[:, 1, 1] = 1
+    Cm[:, 1, 0] = g * np.exp(1j * th)
+    Cm[:, 0, 1] = g * np.exp(-1j * th)
+    ph, lam, flags = gpu_lib.phase_link(torch.from_numpy(Cm).cuda(), ref=0)
+    ph = ph.cpu().numpy()
+    assert np.all(flags.cpu().numpy() == 0)
+    assert np.abs(np.angle(ph[1] * np.exp(-1j * th))).max() < 1e-5
+    np.testing.assert_allclose(lam.cpu().numpy(), 1.0, atol=1e-4)
+
+
+def test_nodata_pixels_are_invalid_and_ragged_grid(gpu_lib):
+    wl = synth.crop("tiny", 37, 43)
+    z = synth.make_stack(wl, seed=23)
+    z[:, 5:9, 7:12] = 0  # nodata block
+    window = (3, 2, 2, 3)  # ragged: 37 = 12*3 + 1, 43 = 21*2 + 1
+    zc = z.cuda()
+    mean, var = gpu_lib.amplitude_stats(zc)
+    mask, count = gpu_lib.shp_select(mean, var, wl.n_new, window, 1e-3)
+    coh = gpu_lib.estimate_coherence(zc, mask, window)
+    ph, lam, flags = gpu_lib.phase_link(coh, ref=0)
+    r = O.link_ministack(z.numpy(), 0, window, 1e-3, 0)
+    np.testing.assert_array_equal(mask.cpu().numpy().view(np.uint32), r["mask"])
+    np.testing.assert_array_equal(flags.cpu().numpy() == 2, r["link"]["flag"] == 2)
+    assert (r["link"]["flag"] == 2).sum() > 0
+    inval = flags.cpu().numpy() == 2
+    assert np.all(ph.cpu().numpy()[:, inval] == 1)
+
+
+def test_max_images_and_single_image(gpu_lib):
+    wl = synth.crop("tiny", 24, 24)
+    rng = np.random.default_rng(24)
+    for N in (1, 32):
+        z = (rng.normal(size=(N, 24, 24)) + 1j * rng.normal(size=(N, 24, 24))).astype(np.complex64)
+        z += 2 * z[:1]
+        window = (2, 2, 2, 2)
+        zc = torch.from_numpy(z).cuda()
+        mean, var = gpu_lib.amplitude_stats(zc)
+        mask, _ = gpu_lib.shp_select(mean, var, N, window, 1e-3)
+        coh = gpu_lib.estimate_coherence(zc, mask, window, precision="bf16")
+        ph, lam, flags = gpu_lib.phase_link(coh, ref=N - 1)
+        r = O.link_ministack(z, 0, window, 1e-3, N - 1)
+        np.testing.assert_array_equal(mask.cpu().numpy().view(np.uint32), r["mask"])
+        d = np.abs(coh.cpu().numpy() - r["coh"])
+        assert np.nanmax(d) < COH_TOL
+        if N == 1:
+            assert np.all(ph.cpu().numpy() == 1)
+
+
+def test_window_larger_than_image(gpu_lib):
+    wl = synth.crop("tiny", 7, 9)
+    z = synth.make_stack(wl, seed=25)
+    window = (11, 5, 1, 1)
+    zc = z.cuda()
+    mean, var = gpu_lib.amplitude_stats(zc)
+    mask, count = gpu_lib.shp_select(mean, var, wl.n_new, window, 1e-3)
+    coh = gpu_lib.estimate_coherence(zc, mask, window)
+    r = O.link_ministack(z.numpy(), 0, window, 1e-3, 0)
+    np.testing.assert_array_equal(mask.cpu().numpy().view(np.uint32), r["mask"])
+    assert np.nanmax(np.abs(coh.cpu().numpy() - r["coh"])) < COH_TOL
+
+
+def test_empty_pixel_list(gpu_lib):
+    coh = torch.zeros((0, 5, 5), dtype=torch.complex64, device="cuda")
+    ph, lam, flags = gpu_lib.phase_link(coh)
+    assert ph.shape == (5, 0)
+
+
+def test_deterministic(gpu_lib):
+    c = case("burst-crop")
+    a = gpu_path(gpu_lib, c, "bf16")
+    b = gpu_path(gpu_lib, c, "bf16")
+    for k in ("mask", "coh", "ph", "kappa"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
