@@ -155,7 +155,7 @@ pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64
  * lambda: [npix] or NULL (eigenvalue of the vector: lambda_min of
  * |C|^{-1} o C for EMI, lambda_max of C for EVD); flags: [npix] or NULL
  * (PL_FLAG_*); invalid pixels (non-finite C) get phasors 1.
- * counters: optional. */
+ * counters: optional.  npix = 0 is a no-op (pointers may then be NULL). */
 pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
                         pl_link_method method, pl_c64* phasors, float* lambda, uint8_t* flags,
                         uint64_t* counters, pl_stream stream);

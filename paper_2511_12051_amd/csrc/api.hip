@@ -163,9 +163,9 @@ pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64
 pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
                         pl_link_method method, pl_c64* phasors, float* lambda, uint8_t* flags,
                         uint64_t* counters, pl_stream stream) {
-    PL_CHECK(coh && phasors, PL_ERR_INVALID_ARG, "pl_phase_link: NULL pointer");
     PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_phase_link: N=%d outside 1..%d", N, kMaxN);
     PL_CHECK(npix >= 0, PL_ERR_SHAPE, "pl_phase_link: negative pixel count");
+    PL_CHECK(npix == 0 || (coh && phasors), PL_ERR_INVALID_ARG, "pl_phase_link: NULL pointer");
     PL_CHECK(ref_idx >= 0 && ref_idx < N, PL_ERR_INVALID_ARG, "pl_phase_link: ref_idx %d outside 0..%d",
              ref_idx, N - 1);
     PL_CHECK(method == PL_LINK_EMI || method == PL_LINK_EVD, PL_ERR_INVALID_ARG,

@@ -16,11 +16,11 @@
 //     mu < lambda_min (Sylvester's inertia), so the iteration converges to the
 //     wanted eigenvector.  EMI starts from mu = 0.99 (Sec. 3.2) and backs off
 //     if the inertia check fails; EVD starts from minus the largest absolute
-//     row sum of C (a Gershgorin bound).  After 3, 6 and 9 iterations the shift
-//     moves up to rho - ||B x - rho x|| (rho the Rayleigh quotient), a bound
-//     that lies below the eigenvalue nearest rho, again accepted only if the
-//     inertia check passes; this keeps the iteration count low when the
-//     eigen-gap is small compared with the distance from 0.99.
+//     row sum of C (a Gershgorin bound).  When the iterate contracts slowly
+//     (checked after 4, 8, 12 and 18 steps) the shift moves up to
+//     rho - f ||B x - rho x|| (rho the Rayleigh quotient, f = 1, 2, 4 until
+//     the inertia check accepts one); this keeps the iteration count low when
+//     the eigen-gap is small compared with the distance from 0.99.
 //  4. zeta_i = x_i conj(x_ref), returned as unit phasors.
 #include <cmath>
 
@@ -31,7 +31,9 @@ namespace {
 
 constexpr double kTauPivot = 1e-6;
 constexpr float kTol2 = 4e-12f;  // squared change of the unit iterate at convergence
-constexpr int kMaxIter = 48;
+constexpr int kMaxIter = 96;
+constexpr float kRefineRate = 0.5f;           // refine the shift when |dx| shrinks slower
+__constant__ float kRefine[3] = {1.f, 2.f, 4.f};  // margins of the refined shifts, in residuals
 constexpr int kBlock = 256;
 
 struct LinkArgs {
@@ -245,32 +247,42 @@ void phase_link_kernel(LinkArgs a) {
     float mu = use_evd ? evd_shift : 0.99f;
 
     // ---- 3. shifted inverse iteration.  One factorisation site serves the
-    // first shift, its back-off schedule, the refined shifts and restoring
-    // the previous factorisation when a refined shift fails the inertia check.
+    // first shift and its back-off schedule, the refined shifts, and restoring
+    // the accepted shift after every refined candidate was rejected.
     float2 m[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) m[j] = make_float2(0.f, 0.f);
     const bool solve = !invalid;
-    float mu_req = mu;           // shift of the pending factorisation
-    bool need = solve;           // this group waits for a factorisation
-    int stage = 0;               // 0..3: first-shift schedule, 4: refining, 5: restoring
+    float mu_req = mu;    // shift of the pending factorisation
+    bool need = solve;    // this group waits for a factorisation
+    int stage = 0;        // 0..3: first-shift schedule, 4: refining, 5: restoring
+    int cand = 0;         // refined candidate rho - kRefine[cand] * res
+    float rho_t = 0.f, res_t = 0.f;
     bool conv = !solve;
     int it = 0, retries = 0;
-    for (int guard = 0; guard < 4 * kMaxIter; ++guard) {
+    float d2prev = 0.f;
+    for (int guard = 0; guard < 2 * kMaxIter; ++guard) {
         if (gany<64>(need, 0)) {
 #pragma unroll
             for (int j = 0; j < NP; ++j) if (need) m[j] = b[j];
             const bool ok = invert_c<NP>(m, mu_req, N, i, need, rbc);
             if (need) {
                 if (ok) {
+                    if (stage == 4) d2prev = 0.f;  // the contraction rate changes
                     mu = mu_req;
                     need = false;
                     stage = stage < 4 ? stage : 4;
-                } else if (stage == 4) {  // refined shift rejected: factor the old one again
+                } else if (stage == 4) {
                     ++retries;
-                    mu_req = mu;
-                    stage = 5;
-                } else if (stage == 5) {  // cannot happen in exact arithmetic; stop here
+                    ++cand;
+                    const float next = cand < 3 ? rho_t - kRefine[cand] * res_t : mu;
+                    if (next > mu) {
+                        mu_req = next;
+                    } else {  // every candidate rejected: factor the accepted shift again
+                        mu_req = mu;
+                        stage = 5;
+                    }
+                } else if (stage == 5) {  // cannot happen in exact arithmetic
                     need = false;
                     conv = true;
                 } else {  // first shift rejected: back off
@@ -300,20 +312,31 @@ void phase_link_kernel(LinkArgs a) {
         const float dx = y.x - x.x, dy = y.y - x.y;
         const float d2 = gsum<NP>(dx * dx + dy * dy);
         const bool finite = n2 > 0.f && n2 <= 3.4e38f;
+        // contraction rate of the iteration (1 until two steps are known)
+        const float q2 = d2prev > 0.f ? d2 / d2prev : 1.f;
         if (!conv) {
             if (finite) x = y;
             if (d2 < kTol2 || !finite) conv = true;
+            d2prev = d2;
         }
         ++it;
-        if (it == 3 || it == 6 || it == 9) {
-            if (gany<64>(!conv, 0)) {
+        if (it == 4 || it == 8 || it == 12 || it == 18) {
+            // slow contraction: move the shift towards lambda_min.  The first
+            // candidate rho - ||Bx - rho x|| bounds the eigenvalue nearest rho
+            // from below; while x still mixes several eigenvectors it can lie
+            // above lambda_min, so larger margins follow if the inertia check
+            // rejects it.
+            const bool slow = !conv && q2 > kRefineRate * kRefineRate;
+            if (gany<64>(slow, 0)) {
                 const float2 bx = matvec<NP>(b, x, i, xb);
                 const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
                 const float rx = bx.x - rho * x.x, ry = bx.y - rho * x.y;
                 const float res = sqrtf(gsum<NP>(rx * rx + ry * ry));
-                const float mu2 = rho - res;
-                if (!conv && mu2 > mu) {
-                    mu_req = mu2;
+                if (slow && rho - res > mu) {
+                    rho_t = rho;
+                    res_t = res;
+                    cand = 0;
+                    mu_req = rho - res;
                     need = true;
                     stage = 4;
                 }

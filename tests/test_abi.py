@@ -67,6 +67,7 @@ def test_argument_errors_return_before_any_device_work(lib):
     # N outside 1..32
     assert lib.pl_estimate_coherence(fake, 33, 8, 8, _w(1, 1, 1, 1), fake, 0, fake, None) == 3
     assert lib.pl_phase_link(fake, 0, 10, 0, 0, fake, None, None, None, None) == 3
+    assert lib.pl_phase_link(None, 5, 0, 0, 0, None, None, None, None, None) == 0
     assert lib.pl_amplitude_stats(fake, 40, 4, 4, fake, fake, None) == 3
     # bad window / shapes
     assert lib.pl_shp_select(fake, fake, 8, 8, 10.0, _w(-1, 1, 1, 1), 1e-3, fake, fake, None, None) == 2
