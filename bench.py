@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -106,20 +108,44 @@ def stage_times(torch, path, steps):
     return {n: v / steps for n, v in acc.items()}
 
 
-def algorithmic(wl, shp_sum, P):
-    """Algorithmic bytes and flops of each stage (one launch each)."""
+def algorithmic(wl, shp_sum, P, prec):
+    """Algorithmic bytes and flops of each stage (one launch each) and the
+    peak each is measured against."""
     R, C, N, M = wl.R, wl.C, wl.N, wl.n_new
     nw = ((2 * wl.window[0] + 1) * (2 * wl.window[1] + 1) + 31) // 32
     px = R * C
+    mfma_peak = PEAK["bf16_mfma_TFLOPs"] if prec == "bf16" else PEAK["fp32_mfma_TFLOPs"]
     return {
         "stats": {"bytes": px * M * 8 + px * 16},
         "glrt": {"bytes": px * 16 + P * nw * 4 + P * 2},
-        # complex MACs over the N(N+1)/2 unique entries of each Hermitian A, 8 flops each
+        # complex MACs over the N(N+1)/2 unique entries of each Hermitian A,
+        # 8 flops each, over the pixel's SHPs
         "coherence": {"bytes": px * N * 8 + P * nw * 4 + P * N * N * 8,
-                      "flops": shp_sum * (N * (N + 1) // 2) * 8},
-        "link": {"bytes": P * N * N * 8 + P * N * 8 + P * 5},
+                      "flops": shp_sum * (N * (N + 1) // 2) * 8, "flop_peak": mfma_peak,
+                      "flop_bound": "mfma"},
+        # EMI per pixel: one N x N FP64 inverse (2 N^3), one complex inverse
+        # (8 N^3) and ten complex mat-vecs (8 N^2 each); vector ALU peak
+        "link": {"bytes": P * N * N * 8 + P * N * 8 + P * 5,
+                 "flops": P * (2 * N ** 3 + 8 * N ** 3 + 10 * 8 * N ** 2),
+                 "flop_peak": PEAK["fp32_valu_TFLOPs"], "flop_bound": "alu"},
         "compress": {"bytes": px * M * 8 + P * N * 8 + px * 8},
     }
+
+
+def roofline(alg, t_ms):
+    """The binding resource of a stage: the larger of its ideal HBM time and
+    its ideal compute time at the published peaks."""
+    t = t_ms * 1e-3
+    t_hbm = alg["bytes"] / (PEAK["hbm_GBps"] * 1e9)
+    t_flop = alg["flops"] / (alg["flop_peak"] * 1e12) if "flops" in alg else 0.0
+    if t_flop > t_hbm:
+        r = {"bound": alg["flop_bound"], "achieved": alg["flops"] / t / 1e12,
+             "peak": alg["flop_peak"], "unit": "TFLOP/s"}
+    else:
+        r = {"bound": "hbm", "achieved": alg["bytes"] / t / 1e9, "peak": PEAK["hbm_GBps"],
+             "unit": "GB/s"}
+    r["frac"] = r["achieved"] / r["peak"]
+    return r
 
 
 def cpu_baseline(wl_name, seed):
@@ -128,7 +154,7 @@ def cpu_baseline(wl_name, seed):
 
     import synth
     from oracle import plink_oracle as O
-    wl = synth.crop(wl_name, 192 if wl_name != "tiny" else 64, 768 if wl_name != "tiny" else 64)
+    wl = synth.crop(wl_name, 576 if wl_name != "tiny" else 64, 1536 if wl_name != "tiny" else 64)
     z = synth.make_stack(wl, seed=seed).numpy()
     t0, c0 = time.perf_counter(), time.process_time()
     r = O.link_ministack(z, wl.n_comp, wl.window, wl.alpha, max(0, wl.n_comp - 1))
@@ -148,6 +174,17 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = 1 << 28  # 2^28 float32 = 1 GiB each way
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": 4 * n, "calibrate_copy_bytes_written": 4 * n,
+                          "launches": 3}))
+        return
 
     import paper_2511_12051_amd as plink
     import synth
@@ -176,22 +213,14 @@ def main():
               file=sys.stderr, flush=True)
 
     main_r = results[args.precision]
-    alg = algorithmic(wl, main_r["shp_sum"], P)
+    alg = algorithmic(wl, main_r["shp_sum"], P, args.precision)
     st = main_r["stages"]
     dom = max(st, key=st.get)
-    t = st[dom] * 1e-3
-    if dom == "coherence" and args.precision == "bf16":
-        roof = {"bound": "mfma", "achieved": alg[dom]["flops"] / t / 1e12,
-                "peak": PEAK["bf16_mfma_TFLOPs"], "unit": "TFLOP/s"}
-    elif dom == "coherence":
-        roof = {"bound": "mfma", "achieved": alg[dom]["flops"] / t / 1e12,
-                "peak": PEAK["fp32_mfma_TFLOPs"], "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": alg[dom]["bytes"] / t / 1e9, "peak": PEAK["hbm_GBps"],
-                "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof = roofline(alg[dom], st[dom])
     roof["traffic"] = None
     roof["kernel"] = dom
+    stage_roof = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
+                      for kk, vv in roofline(alg[k], st[k]).items()} for k in st}
 
     line = {
         "metric": "phase-linked pixels/sec at N=15/25 within 1e-3 rad of FP64 oracle; mixed vs FP32",
@@ -212,6 +241,7 @@ def main():
                    "precision": args.precision},
         "stage_ms": {k: round(v, 4) for k, v in st.items()},
         "roofline": roof,
+        "stage_roofline": stage_roof,
     }
     for prec, r in results.items():
         if prec != args.precision:

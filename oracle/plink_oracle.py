@@ -410,7 +410,8 @@ def sequential(batches, K, window, alpha, method="emi"):
         kappas.append(res["kappa"])
         out.append({"phasor": res["phasor"][len(comp):], "kappa": res["kappa"],
                     "n_comp": len(comp), "ref": ref, "mask": res["mask"],
-                    "flag": res["link"]["flag"], "cond": res["link"]["cond"]})
+                    "flag": res["link"]["flag"], "cond": res["link"]["cond"],
+                    "coh": res["coh"]})
     return out
 
 

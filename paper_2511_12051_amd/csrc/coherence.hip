@@ -55,6 +55,7 @@ struct CohArgs {
     int plane;        // LDS elements per plane
     int wave_words;   // 32-bit words of LDS per wavefront
     int n_pairs;      // pairs per window = (2 hy + 1)(hx + 1)
+    float inv_half_w, inv_n, inv_ppr;  // reciprocals for exact small divisions
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -90,71 +91,156 @@ struct Acc<32> {
     __device__ static int row(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 };
 
-// Stage input row y of the strip into ring slot y mod wy.
-template <bool SPLIT>
-__device__ void load_row(const CohArgs& a, void* lds, int64_t y, int64_t x0, int nthreads) {
+// Row staging.  A "unit" is two horizontally adjacent pixels (x even) of one
+// image in one staged row, so that hi and lo BF16 halves are stored as 32-bit
+// pairs.  Units of the rows [y_first, y_first + nrows) are numbered
+// ((row * N + image) * half_w + pair).
+// units a thread keeps in registers while the current row is computed
+template <int NT>
+constexpr int kPrefetchUnits = NT == 16 ? 8 : 4;
+
+template <int NT>
+struct RowLoad {
+    float2 v[2 * kPrefetchUnits<NT>];
+};
+
+__device__ __forceinline__ int fast_div(int n, float inv) {  // exact for 0 <= n < 2^22
+    return (int)(((float)n + 0.5f) * inv);
+}
+
+__device__ __forceinline__ void fetch_unit(const CohArgs& a, int64_t y_first, int64_t x0, int u,
+                                           float2& z0, float2& z1) {
     const Geometry& g = a.g;
-    const int slot = (int)(((y % g.wy) + g.wy) % g.wy);
-    const bool yin = y >= 0 && y < g.R;
-    const int total = a.N * a.tile_w;
-    for (int idx = threadIdx.x; idx < total; idx += nthreads) {
-        const int d = idx / a.tile_w, lx = idx - d * a.tile_w;
-        const int64_t x = x0 + lx;
-        float2 z = make_float2(0.f, 0.f);
-        if (yin && x >= 0 && x < g.C) z = a.t.p[d][y * g.C + x];
-        const int e = slot * a.pitch + lx;
-        if constexpr (SPLIT) {
-            uint16_t* L = reinterpret_cast<uint16_t*>(lds);
-            uint32_t rh = bf16_bits(z.x), ih = bf16_bits(z.y);
-            uint32_t rl = bf16_bits(z.x - bf16_value(rh)), il = bf16_bits(z.y - bf16_value(ih));
-            L[(0 * a.N + d) * a.plane + e] = (uint16_t)rh;
-            L[(1 * a.N + d) * a.plane + e] = (uint16_t)rl;
-            L[(2 * a.N + d) * a.plane + e] = (uint16_t)ih;
-            L[(3 * a.N + d) * a.plane + e] = (uint16_t)il;
-        } else {
-            float* L = reinterpret_cast<float*>(lds);
-            L[(0 * a.N + d) * a.plane + e] = z.x;
-            L[(1 * a.N + d) * a.plane + e] = z.y;
-        }
+    const int hw = a.tile_w >> 1;
+    const int rd = fast_div(u, a.inv_half_w);  // row * N + image
+    const int px = u - rd * hw;
+    const int r = fast_div(rd, a.inv_n);
+    const int d = rd - r * a.N;
+    const int64_t y = y_first + r, x = x0 + 2 * px;
+    z0 = make_float2(0.f, 0.f);
+    z1 = z0;
+    if (y >= 0 && y < g.R) {
+        const float2* row = a.t.p[d] + y * g.C;
+        if (x >= 0 && x < g.C) z0 = row[x];
+        if (x + 1 >= 0 && x + 1 < g.C) z1 = row[x + 1];
+    }
+}
+
+// Ring slot of input row y (y may be negative above the image).
+__device__ __forceinline__ int ring_slot(int64_t y, int wy) {
+    int s = (int)(y % wy);
+    return s + (s < 0 ? wy : 0);
+}
+
+template <bool SPLIT>
+__device__ __forceinline__ void store_unit(const CohArgs& a, void* lds, int slot_first, int u,
+                                           float2 z0, float2 z1) {
+    const Geometry& g = a.g;
+    const int hw = a.tile_w >> 1;
+    const int rd = fast_div(u, a.inv_half_w);
+    const int px = u - rd * hw;
+    const int r = fast_div(rd, a.inv_n);
+    const int d = rd - r * a.N;
+    int slot = slot_first + r;  // r < 2 wy
+    slot -= slot >= g.wy ? g.wy : 0;
+    slot -= slot >= g.wy ? g.wy : 0;
+    const int e = slot * a.pitch + 2 * px;  // element offset inside a plane (even)
+    if constexpr (SPLIT) {
+        uint32_t* L = reinterpret_cast<uint32_t*>(lds);
+        const uint32_t rh0 = bf16_bits(z0.x), rh1 = bf16_bits(z1.x);
+        const uint32_t ih0 = bf16_bits(z0.y), ih1 = bf16_bits(z1.y);
+        const uint32_t rl0 = bf16_bits(z0.x - bf16_value(rh0)), rl1 = bf16_bits(z1.x - bf16_value(rh1));
+        const uint32_t il0 = bf16_bits(z0.y - bf16_value(ih0)), il1 = bf16_bits(z1.y - bf16_value(ih1));
+        const int hp = a.plane >> 1, w = e >> 1;
+        L[(0 * a.N + d) * hp + w] = rh0 | (rh1 << 16);
+        L[(1 * a.N + d) * hp + w] = rl0 | (rl1 << 16);
+        L[(2 * a.N + d) * hp + w] = ih0 | (ih1 << 16);
+        L[(3 * a.N + d) * hp + w] = il0 | (il1 << 16);
+    } else {
+        float* L = reinterpret_cast<float*>(lds);
+        L[(0 * a.N + d) * a.plane + e] = z0.x;
+        L[(0 * a.N + d) * a.plane + e + 1] = z1.x;
+        L[(1 * a.N + d) * a.plane + e] = z0.y;
+        L[(1 * a.N + d) * a.plane + e + 1] = z1.y;
+    }
+}
+
+// Synchronous staging of rows [y_first, y_first + nrows).
+template <bool SPLIT>
+__device__ void load_rows(const CohArgs& a, void* lds, int64_t y_first, int nrows, int64_t x0,
+                          int nthreads) {
+    const int total = nrows * a.N * (a.tile_w >> 1);
+    const int sf = ring_slot(y_first, a.g.wy);
+    for (int u = threadIdx.x; u < total; u += nthreads) {
+        float2 z0, z1;
+        fetch_unit(a, y_first, x0, u, z0, z1);
+        store_unit<SPLIT>(a, lds, sf, u, z0, z1);
+    }
+}
+
+// Start the global loads of the first kPrefetchUnits units of each thread;
+// they complete while the current row's pixels are computed.
+template <int NT>
+__device__ __forceinline__ void prefetch_rows(const CohArgs& a, RowLoad<NT>& pf, int64_t y_first,
+                                              int nrows, int64_t x0, int nthreads) {
+    const int total = nrows * a.N * (a.tile_w >> 1);
+#pragma unroll
+    for (int k = 0; k < kPrefetchUnits<NT>; ++k) {
+        const int u = threadIdx.x + k * nthreads;
+        if (u < total) fetch_unit(a, y_first, x0, u, pf.v[2 * k], pf.v[2 * k + 1]);
+    }
+}
+
+template <int NT, bool SPLIT>
+__device__ __forceinline__ void commit_rows(const CohArgs& a, void* lds, const RowLoad<NT>& pf,
+                                            int64_t y_first, int nrows, int64_t x0, int nthreads) {
+    const int total = nrows * a.N * (a.tile_w >> 1);
+    const int sf = ring_slot(y_first, a.g.wy);
+#pragma unroll
+    for (int k = 0; k < kPrefetchUnits<NT>; ++k) {
+        const int u = threadIdx.x + k * nthreads;
+        if (u < total) store_unit<SPLIT>(a, lds, sf, u, pf.v[2 * k], pf.v[2 * k + 1]);
+    }
+    // units beyond the register budget (very wide strips) are staged directly
+    for (int u = threadIdx.x + kPrefetchUnits<NT> * nthreads; u < total; u += nthreads) {
+        float2 z0, z1;
+        fetch_unit(a, y_first, x0, u, z0, z1);
+        store_unit<SPLIT>(a, lds, sf, u, z0, z1);
     }
 }
 
 // List the window pairs of output pixel (oy, ox) that hold an SHP.  Entry =
 // (element offset << 2) | (bit0 | bit1 << 1), padded with zero entries to a
-// multiple of `ppk`.  Returns the padded count (uniform over the wave).
-__device__ int build_pairs(const CohArgs& a, uint32_t* table, int64_t oy, int64_t ox, int64_t x0,
-                           int ppk, int lane) {
+// multiple of `ppk`.  `mw` holds mask word `lane` of the pixel (lanes < nw);
+// `s0` is the ring slot of the window's first row.  Returns the padded count
+// (uniform over the wave).
+__device__ int build_pairs(const CohArgs& a, uint32_t* table, int64_t ox, int64_t x0, int s0,
+                           uint32_t mw, int ppk, int lane) {
     const Geometry& g = a.g;
-    const int64_t cy = oy * g.sy + g.sy / 2, cx = ox * g.sx + g.sx / 2;
+    const int64_t cx = ox * g.sx + g.sx / 2;
     const int rel = (int)(cx - g.hx - x0);  // >= 0 by construction of x0
     const int xs = rel & ~1, par = rel & 1;
     const int ppr = g.hx + 1;  // pairs per window row
-    const uint32_t* m = a.mask + (oy * g.oC + ox) * g.nw;
     int n = 0;
     for (int base = 0; base < a.n_pairs; base += 64) {
         const int j = base + lane;
-        uint32_t entry = 0;
-        bool keep = false;
+        const int dy = fast_div(j, a.inv_ppr), px = j - dy * ppr;
+        const int dx0 = 2 * px - par;
+        const int b0 = dy * g.wx + dx0;
+        // bits b0 and b0 + 1 of the window mask (pairs never straddle rows)
+        const uint32_t w0 = __shfl(mw, (b0 >= 0 ? b0 : 0) >> 5, 64);
+        const uint32_t w1 = __shfl(mw, (b0 + 1) >> 5, 64);
+        uint32_t bits = 0;
         if (j < a.n_pairs) {
-            const int dy = j / ppr, px = j - dy * ppr;
-            const int64_t y = cy - g.hy + dy;
-            const int slot = (int)(((y % g.wy) + g.wy) % g.wy);
-            const int dx0 = 2 * px - par, dx1 = dx0 + 1;
-            uint32_t bits = 0;
-            if (dx0 >= 0) {
-                const int b = dy * g.wx + dx0;
-                bits |= (m[b >> 5] >> (b & 31)) & 1u;
-            }
-            if (dx1 <= 2 * g.hx) {
-                const int b = dy * g.wx + dx1;
-                bits |= ((m[b >> 5] >> (b & 31)) & 1u) << 1;
-            }
-            keep = bits != 0;
-            entry = ((uint32_t)(slot * a.pitch + xs + 2 * px) << 2) | bits;
+            if (dx0 >= 0) bits |= (w0 >> (b0 & 31)) & 1u;
+            if (dx0 + 1 <= 2 * g.hx) bits |= ((w1 >> ((b0 + 1) & 31)) & 1u) << 1;
         }
+        int slot = s0 + dy;
+        slot -= slot >= g.wy ? g.wy : 0;
+        const bool keep = bits != 0;
         const uint64_t bal = __ballot(keep);
         const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-        if (keep) table[n + before] = entry;
+        if (keep) table[n + before] = ((uint32_t)(slot * a.pitch + xs + 2 * px) << 2) | bits;
         n += __popcll(bal);
     }
     const int npad = (n + ppk - 1) / ppk * ppk;
@@ -219,52 +305,74 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
         constexpr int PPK = NT == 16 ? 16 : 8;  // pairs per k-step
         const uint32_t* L = reinterpret_cast<const uint32_t*>(lds);
         const int half_plane = a.plane >> 1;  // plane stride in 32-bit words
-        const uint32_t* prh = L + (0 * a.N + d) * half_plane;
-        const uint32_t* prl = L + (1 * a.N + d) * half_plane;
-        const uint32_t* pih = L + (2 * a.N + d) * half_plane;
-        const uint32_t* pil = L + (3 * a.N + d) * half_plane;
+        const int dd = live ? d : a.N - 1;
+        const uint32_t* prh = L + (0 * a.N + dd) * half_plane;
+        const uint32_t* prl = L + (1 * a.N + dd) * half_plane;
+        const uint32_t* pih = L + (2 * a.N + dd) * half_plane;
+        const uint32_t* pil = L + (3 * a.N + dd) * half_plane;
+        // Dead rows (image index >= N) read a valid plane and are masked to
+        // zero on the A side; their garbage B columns are never stored.
+        const uint32_t live_mask = live ? 0xffffffffu : 0u;
+        // software pipeline: the LDS reads of step ks + PPK are issued before
+        // the MFMAs of step ks
+        u32x4 e = *reinterpret_cast<const u32x4*>(table + 4 * g);
+        u32x4 rh, rl, ih, il;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t off = e[t] >> 3;  // element offset / 2 = word offset
+            rh[t] = prh[off];
+            rl[t] = prl[off];
+            ih[t] = pih[off];
+            il[t] = pil[off];
+        }
         for (int ks = 0; ks < npad; ks += PPK) {
-            const u32x4 e = *reinterpret_cast<const u32x4*>(table + ks + 4 * g);
-            u32x4 rh, rl, ih, il, rhm, ihm;
+            u32x4 en = e, nrh = rh, nrl = rl, nih = ih, nil = il;
+            if (ks + PPK < npad) {
+                en = *reinterpret_cast<const u32x4*>(table + ks + PPK + 4 * g);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t off = en[t] >> 3;
+                    nrh[t] = prh[off];
+                    nrl[t] = prl[off];
+                    nih[t] = pih[off];
+                    nil[t] = pil[off];
+                }
+            }
+            u32x4 rhm, ihm;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                const uint32_t off = e[t] >> 3;  // element offset / 2 = word offset
                 const uint32_t bits = e[t] & 3u;
-                const uint32_t msk = ((bits & 1u) ? 0x0000ffffu : 0u) | ((bits & 2u) ? 0xffff0000u : 0u);
-                uint32_t xrh = 0, xrl = 0, xih = 0, xil = 0;
-                if (live) {
-                    xrh = prh[off];
-                    xrl = prl[off];
-                    xih = pih[off];
-                    xil = pil[off];
-                }
-                rh[t] = xrh;
-                rl[t] = xrl;
-                ih[t] = xih;
-                il[t] = xil;
-                rhm[t] = xrh & msk;
-                ihm[t] = xih & msk;
+                const uint32_t msk = (((bits & 1u) ? 0x0000ffffu : 0u) | ((bits & 2u) ? 0xffff0000u : 0u)) & live_mask;
+                rhm[t] = rh[t] & msk;
+                ihm[t] = ih[t] & msk;
             }
             const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh), Rl = __builtin_bit_cast(bf16x8, rl);
             const bf16x8 Ih = __builtin_bit_cast(bf16x8, ih), Il = __builtin_bit_cast(bf16x8, il);
             const bf16x8 Rm = __builtin_bit_cast(bf16x8, rhm), Im = __builtin_bit_cast(bf16x8, ihm);
+            // the four accumulation chains are interleaved so that no MFMA
+            // waits on the one just issued
             if constexpr (NT == 16) {
                 whh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Rh, whh, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Ih, whh, 0, 0, 0);
                 whl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Rl, whl, 0, 0, 0);
-                whl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Il, whl, 0, 0, 0);
                 v1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Ih, v1, 0, 0, 0);
-                v1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Il, v1, 0, 0, 0);
                 v2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Rl, v2, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Ih, whh, 0, 0, 0);
+                whl = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Im, Il, whl, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Rm, Il, v1, 0, 0, 0);
             } else {
                 whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Rh, whh, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Ih, whh, 0, 0, 0);
                 whl = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Rl, whl, 0, 0, 0);
-                whl = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Il, whl, 0, 0, 0);
                 v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Ih, v1, 0, 0, 0);
-                v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Il, v1, 0, 0, 0);
                 v2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Rl, v2, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Ih, whh, 0, 0, 0);
+                whl = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Il, whl, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Il, v1, 0, 0, 0);
             }
+            e = en;
+            rh = nrh;
+            rl = nrl;
+            ih = nih;
+            il = nil;
         }
         AT t;
         transpose_read<NT>(S, whl, t, lane);
@@ -275,28 +383,25 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
     } else {
         constexpr int SPK = NT == 16 ? 4 : 2;  // samples per k-step
         const float* L = reinterpret_cast<const float*>(lds);
-        const float* pr = L + (0 * a.N + d) * a.plane;
-        const float* pi = L + (1 * a.N + d) * a.plane;
+        const int dd = live ? d : a.N - 1;
+        const float* pr = L + (0 * a.N + dd) * a.plane;
+        const float* pi = L + (1 * a.N + dd) * a.plane;
         const int half = g & 1;
         const int eoff = g >> 1;  // which pair of the k-step (16x16x4 only)
         for (int ks = 0; ks < npad; ks += SPK / 2) {
             const uint32_t e = table[ks + eoff];
             const uint32_t off = (e >> 2) + half;
-            const bool on = (e >> half) & 1u;
-            float r = 0.f, im_ = 0.f;
-            if (live) {
-                r = pr[off];
-                im_ = pi[off];
-            }
+            const bool on = live && ((e >> half) & 1u);
+            const float r = pr[off], im_ = pi[off];
             const float rm = on ? r : 0.f, imm = on ? im_ : 0.f;
             if constexpr (NT == 16) {
                 whh = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, r, whh, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(imm, im_, whh, 0, 0, 0);
                 v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, im_, v1, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(imm, im_, whh, 0, 0, 0);
             } else {
                 whh = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, r, whh, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(imm, im_, whh, 0, 0, 0);
                 v1 = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, im_, v1, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(imm, im_, whh, 0, 0, 0);
             }
         }
         re = whh;
@@ -325,21 +430,39 @@ __global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
     float* S = reinterpret_cast<float*>(wave_area);
     constexpr int PPK = SPLIT ? (NT == 16 ? 16 : 8) : (NT == 16 ? 2 : 1);
 
-    int64_t loaded_to = INT64_MIN;  // first input row not yet staged
+    // ring slot of the first window row of output row oy
+    auto first_slot = [&](int64_t oy) {
+        int s0 = (int)((oy * g.sy + g.sy / 2 - g.hy) % g.wy);
+        return s0 + (s0 < 0 ? g.wy : 0);
+    };
+    RowLoad<NT> pf;
+    // prologue: the full window of the first output row
+    load_rows<SPLIT>(a, lds_words, oy0 * g.sy + g.sy / 2 - g.hy, g.wy, x0, nthreads);
+    __syncthreads();
     for (int64_t oy = oy0; oy < oy1; ++oy) {
         const int64_t cy = oy * g.sy + g.sy / 2;
-        int64_t yfirst = cy - g.hy;
-        if (loaded_to > yfirst) yfirst = loaded_to;
-        __syncthreads();
-        for (int64_t y = yfirst; y <= cy + g.hy; ++y) load_row<SPLIT>(a, lds_words, y, x0, nthreads);
-        loaded_to = cy + g.hy + 1;
-        __syncthreads();
-        for (int64_t ox = ox0 + wave; ox < ox1; ox += nwaves) {
-            const int npad = build_pairs(a, wave_area, oy, ox, x0, PPK, lane);
+        // rows the next output row needs that are not staged yet
+        const int64_t next_first = (cy + g.hy + 1) > (cy + g.sy - g.hy) ? (cy + g.hy + 1) : (cy + g.sy - g.hy);
+        const int next_rows = (int)((cy + g.sy + g.hy) - next_first + 1);
+        const bool more = oy + 1 < oy1;
+        if (more) prefetch_rows<NT>(a, pf, next_first, next_rows, x0, nthreads);
+        const int s0 = first_slot(oy);
+        int64_t ox = ox0 + wave;
+        uint32_t mw = 0;
+        if (ox < ox1 && lane < g.nw) mw = a.mask[(oy * g.oC + ox) * g.nw + lane];
+        for (; ox < ox1; ox += nwaves) {
+            const uint32_t mcur = mw;
+            if (ox + nwaves < ox1 && lane < g.nw) mw = a.mask[(oy * g.oC + ox + nwaves) * g.nw + lane];
+            const int npad = build_pairs(a, wave_area, ox, x0, s0, mcur, PPK, lane);
             wave_sync();
             typename Acc<NT>::T re, im;
             pixel_gram<NT, SPLIT>(a, lds_words, wave_area, npad, lane, re, im, S);
             store_pixel<NT>(a, S, re, im, oy * g.oC + ox, lane);
+        }
+        __syncthreads();  // every wave is done with the rows about to be replaced
+        if (more) {
+            commit_rows<NT, SPLIT>(a, lds_words, pf, next_first, next_rows, x0, nthreads);
+            __syncthreads();
         }
     }
 }
@@ -378,6 +501,9 @@ pl_status launch_variant(const CohArgs& a0, hipStream_t s) {
     }
     if (!chosen) return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: window too large for LDS");
     a.TXo = chosen;
+    a.inv_half_w = 1.0f / (float)(a.tile_w >> 1);
+    a.inv_n = 1.0f / (float)a.N;
+    a.inv_ppr = 1.0f / (float)(g.hx + 1);
     const int nwaves = chosen < kMaxWaves ? chosen : kMaxWaves;
     const int64_t n_strips = (g.oC + chosen - 1) / chosen;
     // enough workgroups to fill the chip several times over

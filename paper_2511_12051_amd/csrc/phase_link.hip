@@ -48,27 +48,38 @@ struct LinkArgs {
     unsigned long long* counters;
 };
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
 }
 
+// Reductions over the NP lanes of a group.  Within a row of 16 lanes they use
+// DPP lane permutations (quad swaps, half-row and row mirrors), so no LDS
+// round trip is needed; a 32-lane group adds one exchange between rows.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
 template <int NP>
 __device__ __forceinline__ float gsum(float v) {
+    v += dpp<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);  // row_half_mirror
+    v += dpp<0x140>(v);  // row_mirror
 #pragma unroll
-    for (int o = NP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 16; o < NP; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
 template <int NP>
 __device__ __forceinline__ float gmax(float v) {
+    v = fmaxf(v, dpp<0xb1>(v));
+    v = fmaxf(v, dpp<0x4e>(v));
+    v = fmaxf(v, dpp<0x141>(v));
+    v = fmaxf(v, dpp<0x140>(v));
 #pragma unroll
-    for (int o = NP / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    for (int o = 16; o < NP; o <<= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
 }
 
@@ -83,44 +94,66 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place complex Gauss-Jordan inversion of the Hermitian matrix (m - mu I),
-// row i of m being this lane's m[].  Lanes with act == false keep m unchanged.  Returns
-// (per group) whether every pivot was positive and finite.
-// The shift mu is subtracted from each diagonal entry when its row becomes
-// the pivot: earlier steps only add multiples of pivot rows to it, so this is
-// the same as shifting the matrix first.
+// FP64 counterpart of publish_c without a shift.
 template <int NP>
-__device__ bool invert_c(float2 (&m)[NP], float mu, int N, int i, bool act, float2* rb) {
+__device__ __forceinline__ void publish_d(double (&g)[NP], int k, double* buf) {
+    const double p = g[k];
+    const double inv = 1.0 / p;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) g[j] *= inv;
+    g[k] = inv;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) buf[j] = g[j];
+    buf[NP] = p;
+}
+
+// Scales this lane's row k by 1/p, p = m[k] - mu, stores 1/p at k (in-place
+// Gauss-Jordan form) and publishes the row and p for the group.
+template <int NP>
+__device__ __forceinline__ void publish_c(float2 (&m)[NP], int k, float mu, float2* buf) {
+    const float p = m[k].x - mu;
+    const float inv = 1.0f / p;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) m[j] = make_float2(m[j].x * inv, m[j].y * inv);
+    m[k] = make_float2(inv, 0.f);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) buf[j] = m[j];
+    buf[NP] = make_float2(p, 0.f);
+}
+
+// In-place complex Gauss-Jordan inversion of the Hermitian matrix (m - mu I),
+// row i of m being this lane's m[].  Lanes with act == false keep m unchanged.
+// Returns (per group) whether every pivot was positive and finite.
+// The shift is subtracted from each diagonal entry when its row becomes the
+// pivot: earlier steps only add multiples of pivot rows to it, so this equals
+// shifting first.  The lane owning row k+1 scales and publishes it right after
+// its step-k update (double-buffered), so each step costs one LDS round trip.
+// All lanes of a group belong to one wavefront and its LDS operations execute
+// in program order, so no barrier is needed between publishing and reading.
+template <int NP>
+__device__ bool invert_c(float2 (&m)[NP], float mu, int N, int i, bool act, float2* rb0, float2* rb1) {
     bool pd = true;
+    if (act && i == 0) publish_c<NP>(m, 0, mu, rb0);
 #pragma unroll NP
     for (int k = 0; k < NP; ++k) {
         if (k < N) {
-            if (i == k && act) {
-                const float p = m[k].x - mu;
-                const float inv = 1.0f / p;
-#pragma unroll
-                for (int j = 0; j < NP; ++j) m[j] = make_float2(m[j].x * inv, m[j].y * inv);
-                m[k] = make_float2(inv, 0.f);
-#pragma unroll
-                for (int j = 0; j < NP; ++j) rb[j] = m[j];
-                rb[NP] = make_float2(p, 0.f);
-            }
-            wave_sync();
+            const float2* buf = (k & 1) ? rb1 : rb0;
+            float2* nbuf = (k & 1) ? rb0 : rb1;
             if (act) {
-                const float p = rb[NP].x;
+                const float p = buf[NP].x;
                 pd = pd && (p > 0.f) && (p <= 3.4e38f);
                 if (i != k) {
                     const float2 f = m[k];
                     m[k] = make_float2(0.f, 0.f);
 #pragma unroll
                     for (int j = 0; j < NP; ++j) {
-                        const float2 r = rb[j];
+                        const float2 r = buf[j];
                         m[j].x = fmaf(-f.x, r.x, fmaf(f.y, r.y, m[j].x));
                         m[j].y = fmaf(-f.x, r.y, fmaf(-f.y, r.x, m[j].y));
                     }
                 }
+                if (k + 1 < N && i == k + 1) publish_c<NP>(m, (k + 1 < NP ? k + 1 : NP - 1), mu, nbuf);
             }
-            wave_sync();
         }
     }
     return pd;
@@ -128,8 +161,7 @@ __device__ bool invert_c(float2 (&m)[NP], float mu, int N, int i, bool act, floa
 
 template <int NP>
 __device__ __forceinline__ float2 matvec(const float2 (&m)[NP], float2 x, int i, float2* xb) {
-    xb[i] = x;
-    wave_sync();
+    xb[i] = x;  // read back below by the other lanes (in-order LDS)
     float2 y = make_float2(0.f, 0.f);
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -137,25 +169,28 @@ __device__ __forceinline__ float2 matvec(const float2 (&m)[NP], float2 x, int i,
         y.x = fmaf(m[j].x, v.x, fmaf(-m[j].y, v.y, y.x));
         y.y = fmaf(m[j].x, v.y, fmaf(m[j].y, v.x, y.y));
     }
-    wave_sync();
     return y;
 }
 
 template <int NP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, NP == 16 ? 4 : 2)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
 void phase_link_kernel(LinkArgs a) {
     constexpr int GPW = 64 / NP;  // groups (pixels) per wavefront
-    // per group: GJ row buffer (NP + 2 doubles) and iterate buffer (NP float2)
-    constexpr int GROUP_BYTES = (NP + 2) * 8 + NP * 8;
+    // per group: two GJ pivot-row buffers (NP + 2 doubles each, also used as
+    // NP + 2 float2) and the iterate buffer (NP float2)
+    constexpr int ROW_BYTES = (NP + 2) * 8;
+    constexpr int GROUP_BYTES = 2 * ROW_BYTES + NP * 8;
     __shared__ __attribute__((aligned(16))) unsigned char lds[(kBlock / 64) * GPW * GROUP_BYTES];
     const int lane = lane_id();
     const int i = lane & (NP - 1);
     const int grp = lane / NP;
     const int wave = threadIdx.x >> 6;
     unsigned char* gbase = lds + (wave * GPW + grp) * GROUP_BYTES;
-    double* rbd = reinterpret_cast<double*>(gbase);
-    float2* rbc = reinterpret_cast<float2*>(gbase);
-    float2* xb = reinterpret_cast<float2*>(gbase + (NP + 2) * 8);
+    double* rbd0 = reinterpret_cast<double*>(gbase);
+    double* rbd1 = reinterpret_cast<double*>(gbase + ROW_BYTES);
+    float2* rbc0 = reinterpret_cast<float2*>(gbase);
+    float2* rbc1 = reinterpret_cast<float2*>(gbase + ROW_BYTES);
+    float2* xb = reinterpret_cast<float2*>(gbase + 2 * ROW_BYTES);
 
     const int N = a.N;
     const int64_t pix = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * GPW + grp;
@@ -207,37 +242,41 @@ void phase_link_kernel(LinkArgs a) {
     const bool do_emi = !use_evd && !invalid;
     bool gfail = false;
     if (gany<64>(do_emi, 0)) {
+        // same scheme as invert_c: the owner of row k+1 publishes it after
+        // its step-k update, double-buffered
+        if (do_emi && i == 0) publish_d<NP>(gi, 0, rbd0);
 #pragma unroll NP
         for (int k = 0; k < NP; ++k) {
             if (k < N) {
-                if (i == k && do_emi) {
-                    const double p = gi[k];
-                    const double inv = 1.0 / p;
-#pragma unroll
-                    for (int j = 0; j < NP; ++j) gi[j] *= inv;
-                    gi[k] = inv;
-#pragma unroll
-                    for (int j = 0; j < NP; ++j) rbd[j] = gi[j];
-                    rbd[NP] = p;
-                }
-                wave_sync();
+                const double* buf = (k & 1) ? rbd1 : rbd0;
+                double* nbuf = (k & 1) ? rbd0 : rbd1;
                 if (do_emi) {
-                    const double p = rbd[NP];
+                    const double p = buf[NP];
                     gfail = gfail || !(p > kTauPivot && p <= 1.7976931348623157e308);
                     if (i != k) {
                         const double f = gi[k];
                         gi[k] = 0.0;
 #pragma unroll
-                        for (int j = 0; j < NP; ++j) gi[j] = fma(-f, rbd[j], gi[j]);
+                        for (int j = 0; j < NP; ++j) gi[j] = fma(-f, buf[j], gi[j]);
                     }
+                    if (k + 1 < N && i == k + 1) publish_d<NP>(gi, (k + 1 < NP ? k + 1 : NP - 1), nbuf);
                 }
-                wave_sync();
             }
         }
     }
     use_evd = use_evd || gfail;
 
-    // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted
+    // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
+    // of C is read again (an L2 hit) rather than kept live across step 1.
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        c[j] = make_float2(0.f, 0.f);
+        if (row_live && j < N) {
+            const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src) + j);
+            c[j] = make_float2(v.x, v.y);
+        }
+    }
     float2 b[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
@@ -265,7 +304,7 @@ void phase_link_kernel(LinkArgs a) {
         if (gany<64>(need, 0)) {
 #pragma unroll
             for (int j = 0; j < NP; ++j) if (need) m[j] = b[j];
-            const bool ok = invert_c<NP>(m, mu_req, N, i, need, rbc);
+            const bool ok = invert_c<NP>(m, mu_req, N, i, need, rbc0, rbc1);
             if (need) {
                 if (ok) {
                     if (stage == 4) d2prev = 0.f;  // the contraction rate changes

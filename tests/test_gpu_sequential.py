@@ -1,0 +1,160 @@
+"""GPU sequential estimator (mini-stack reference scheme) against the oracle's
+sequential driver, plus append-only, checkpoint/resume and reference
+inheritance."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import plink_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+PHASE_TOL = 1e-3
+EPS = {"fp32": 2e-6, "bf16": 2e-5}  # coherence error of each path (measured bound x2)
+SAFETY = 3.0
+
+
+def _sequence(R=96, C=198, ministacks=5, seed=31):
+    wl = synth.crop("sequential", R, C)
+    z = synth.make_sequence(wl, seed=seed, ministacks=ministacks)
+    return wl, z
+
+
+def _run_gpu(plink, wl, z, K, prec="fp32", ministacks=None, state=None, start=0):
+    M = wl.n_new
+    n = z.shape[0] // M if ministacks is None else ministacks
+    seq = plink.Sequential(wl.R, wl.C, M, K, wl.window, wl.alpha, precision=prec)
+    if state is not None:
+        seq.load_state(state)
+    zc = z.cuda()
+    outs = []
+    for k in range(start, n):
+        ph, kap, fl = seq.push(zc[k * M:(k + 1) * M].contiguous(), want_flags=True)
+        outs.append((ph.cpu().numpy(), kap.cpu().numpy(), fl.cpu().numpy()))
+    torch.cuda.synchronize()
+    return seq, outs
+
+
+_oracle_cache = {}
+
+
+def _oracle_sequence(wl, z, K, n):
+    key = (wl.name, wl.R, wl.C, K, n, float(z[0, 0, 0].real))
+    if key not in _oracle_cache:
+        M = wl.n_new
+        print(f"[seq] oracle on {wl.R}x{wl.C}, {n} mini-stacks", flush=True)
+        _oracle_cache[key] = O.sequential([z[k * M:(k + 1) * M].numpy() for k in range(n)], K,
+                                          wl.window, wl.alpha)
+    return _oracle_cache[key]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_sequential_teacher_forced(gpu_lib, prec):
+    """Each mini-stack on the GPU fed the oracle's compressed SLCs: masks
+    bit-exact, phases within tolerance on well-posed pixels."""
+    wl, z = _sequence()
+    M, K, n = wl.n_new, 3, 5  # the ring of compressed SLCs wraps
+    orc = _oracle_sequence(wl, z, K, n)
+    zc = z.cuda()
+    stats = [gpu_lib.amplitude_stats(zc[k * M:(k + 1) * M].contiguous()) for k in range(n)]
+    for k in range(n):
+        nc = min(k, K)
+        comp = [torch.from_numpy(orc[j]["kappa"].astype(np.complex64)) for j in range(k - nc, k)]
+        stack = torch.cat([torch.stack(comp).cuda(), zc[k * M:(k + 1) * M]]) if nc else zc[k * M:(k + 1) * M]
+        stack = stack.contiguous()
+        grp = stats[k - nc:k + 1]
+        mean, var = gpu_lib.merge_amplitude_stats(torch.stack([g[0] for g in grp]),
+                                                  torch.stack([g[1] for g in grp]), [M] * len(grp))
+        mask, _ = gpu_lib.shp_select(mean, var, M * len(grp), wl.window, wl.alpha)
+        coh = gpu_lib.estimate_coherence(stack, mask, wl.window, precision=prec)
+        ref = nc - 1 if nc else 0
+        ph, _, fl = gpu_lib.phase_link(coh, ref=ref)
+        o = orc[k]
+        np.testing.assert_array_equal(mask.cpu().numpy().view(np.uint32), o["mask"])
+        cg = coh.cpu().numpy().astype(np.complex128)
+        dC = np.abs(cg - o["coh"]).reshape(len(cg), -1)
+        eps = np.maximum(np.nanmax(np.where(np.isfinite(dC), dC, 0), axis=1), 1e-6)
+        sens = O.phase_sensitivity(o["coh"], ref=ref)
+        fl = fl.cpu().numpy()
+        wp = (SAFETY * sens * eps <= PHASE_TOL) & (fl == o["flag"])
+        err = np.abs(np.angle(ph.cpu().numpy()[nc:] * np.conj(o["phasor"].reshape(M, -1))))
+        print(f"[seq] teacher-forced {prec} mini-stack {k} (K={nc}): well-posed {wp.mean():.3f}, "
+              f"max err {err[:, wp].max():.2e}")
+        assert wp.mean() > 0.8
+        assert err[:, wp].max() <= PHASE_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_sequential_free_running(gpu_lib, prec):
+    """The GPU driver on its own compressed SLCs.  Differences in earlier
+    compressed SLCs enter later mini-stacks as input differences, so this
+    checks the distribution: most valid pixels stay within the tolerance."""
+    wl, z = _sequence()
+    M, K, n = wl.n_new, 3, 5
+    orc = _oracle_sequence(wl, z, K, n)
+    _, outs = _run_gpu(gpu_lib, wl, z, K, prec)
+    for k, (o, (ph, kap, fl)) in enumerate(zip(orc, outs)):
+        assert o["n_comp"] == min(k, K)
+        valid = o["flag"] != O.FLAG_INVALID
+        err = np.abs(np.angle(ph * np.conj(o["phasor"]))).reshape(M, -1)[:, valid]
+        within = np.mean(np.all(err <= PHASE_TOL, axis=0))
+        print(f"[seq] free-running {prec} mini-stack {k}: within 1e-3 rad {within:.4f}, "
+              f"median {np.median(err):.2e}")
+        assert within >= 0.95
+        assert np.median(err) <= 1e-4
+
+
+def test_append_only_and_resume_bit_identical(gpu_lib):
+    wl, z = _sequence(seed=32, ministacks=4)
+    K = 2
+    seq, full = _run_gpu(gpu_lib, wl, z, K, ministacks=4)
+    # earlier outputs are unchanged by later pushes
+    _, two = _run_gpu(gpu_lib, wl, z, K, ministacks=2)
+    for a, b in zip(full[:2], two):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    # checkpoint after two mini-stacks, resume in a fresh driver
+    seq2, _ = _run_gpu(gpu_lib, wl, z, K, ministacks=2)
+    state = seq2.save()
+    assert seq2.count == 2
+    seq3, rest = _run_gpu(gpu_lib, wl, z, K, ministacks=4, state=state, start=2)
+    assert seq3.count == 4
+    for a, b in zip(full[2:], rest):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_checkpoint_rejects_other_geometry(gpu_lib):
+    wl, z = _sequence(seed=33, ministacks=1)
+    seq, _ = _run_gpu(gpu_lib, wl, z, 2, ministacks=1)
+    state = seq.save()
+    other = gpu_lib.Sequential(wl.R, wl.C, wl.n_new, 3, wl.window)
+    with pytest.raises(gpu_lib.PlinkError):
+        other.load_state(state)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_coherent_sequence_referenced_to_day_one(gpu_lib, prec):
+    """Epoch phases shared by every pixel and one common scatterer per pixel:
+    every linked phase equals phi_i - phi_0 (day 1) and every compressed SLC
+    keeps the phase of the first one (reference inheritance, Sec. 2.2)."""
+    rng = np.random.default_rng(35)
+    M, K, n, R, C, w = 15, 3, 5, 36, 60, (5, 2, 3, 3)
+    phi = np.cumsum(rng.uniform(-1, 1, n * M))
+    amp = rng.normal(size=(R, C)) + 1j * rng.normal(size=(R, C))
+    z = torch.from_numpy((np.exp(1j * phi)[:, None, None] * amp[None]).astype(np.complex64))
+    seq = gpu_lib.Sequential(R, C, M, K, w, precision=prec)
+    zc = z.cuda()
+    k0 = None
+    for k in range(n):
+        ph, kap, fl = seq.push(zc[k * M:(k + 1) * M].contiguous(), want_flags=True)
+        ph, kap = ph.cpu().numpy(), kap.cpu().numpy().astype(np.complex128)
+        want = np.exp(1j * (phi[k * M:(k + 1) * M] - phi[0]))[:, None, None]
+        err = np.abs(np.angle(ph * np.conj(want)))
+        k0 = kap if k0 is None else k0
+        inh = np.abs(np.angle(kap * np.conj(k0)))
+        print(f"[seq] coherent {prec} mini-stack {k}: max phase err {err.max():.2e}, "
+              f"max inheritance {inh.max():.2e}")
+        assert err.max() < 2e-3
+        assert inh.max() < 2e-3
