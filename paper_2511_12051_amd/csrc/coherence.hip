@@ -20,14 +20,16 @@
 //
 // Data movement: a workgroup owns a strip of TXo output columns and walks
 // down a band of output rows.  The window rows it needs live in an LDS ring
-// of (2*half_y+1) input rows, planar per (component, image) so that the 16
-// or 32 lanes of one fragment read 16 or 32 different planes at one offset
-// (plane strides are odd in 32-bit words: no bank conflicts).  Moving to the
-// next output row loads only the stride_y new input rows.  Every window is
-// cut into pairs of horizontally adjacent pixels starting at an even column,
-// so one 32-bit LDS read yields two BF16 samples; per pixel a wavefront first
-// lists the pairs that hold at least one SHP (LDS offset + 2 SHP bits), then
-// runs the MFMA loop over that compacted list.
+// of (2*half_y+1) input rows, one plane per image, so that the 16 or 32
+// lanes of one fragment read 16 or 32 different planes at one offset (the
+// plane stride is 4 mod 64 words: the lanes of a group hit distinct banks).
+// Moving to the next output row loads only the stride_y new input rows.  The
+// plane stores 16-byte records of two horizontally adjacent pixels starting
+// at an even column: {re_hi, re_lo, im_hi, im_lo} as BF16 pairs, or
+// {re, im, re, im} in FP32.  Every window is cut into such pairs; per pixel a
+// wavefront first lists the pairs that hold at least one SHP (record offset
+// and a mask word), then runs the MFMA loop over that compacted list with one
+// 16-byte LDS read per pair.
 #include <cmath>
 
 #include "internal.hpp"
@@ -40,7 +42,10 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kMaxWaves = 8;
+#ifndef PL_COH_WAVES
+#define PL_COH_WAVES 8
+#endif
+constexpr int kMaxWaves = PL_COH_WAVES;  // wavefronts per workgroup (one workgroup per CU)
 
 struct CohArgs {
     PlaneTable t;
@@ -50,12 +55,13 @@ struct CohArgs {
     float2* coh;
     int TXo;          // output columns per strip
     int rows_per_wg;  // output rows per workgroup
-    int tile_w;       // staged input columns
-    int pitch;        // LDS elements per staged row
-    int plane;        // LDS elements per plane
+    int tile_w;       // staged input columns (even)
+    int pitch;        // records (pixel pairs) per staged row = tile_w / 2
+    int plane;        // records per image plane (wy * pitch, padded)
     int wave_words;   // 32-bit words of LDS per wavefront
     int n_pairs;      // pairs per window = (2 hy + 1)(hx + 1)
-    float inv_half_w, inv_n, inv_ppr;  // reciprocals for exact small divisions
+    float inv_ppr;    // 1 / (hx + 1), for exact small divisions
+    int vec_rows;     // every image row starts 16-byte aligned (pairs load as 16 bytes)
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -91,135 +97,171 @@ struct Acc<32> {
     __device__ static int row(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 };
 
-// Row staging.  A "unit" is two horizontally adjacent pixels (x even) of one
-// image in one staged row, so that hi and lo BF16 halves are stored as 32-bit
-// pairs.  Units of the rows [y_first, y_first + nrows) are numbered
-// ((row * N + image) * half_w + pair).
-// units a thread keeps in registers while the current row is computed
-template <int NT>
-constexpr int kPrefetchUnits = NT == 16 ? 8 : 4;
-
-template <int NT>
-struct RowLoad {
-    float2 v[2 * kPrefetchUnits<NT>];
-};
-
 __device__ __forceinline__ int fast_div(int n, float inv) {  // exact for 0 <= n < 2^22
     return (int)(((float)n + 0.5f) * inv);
 }
 
-__device__ __forceinline__ void fetch_unit(const CohArgs& a, int64_t y_first, int64_t x0, int u,
-                                           float2& z0, float2& z1) {
-    const Geometry& g = a.g;
-    const int hw = a.tile_w >> 1;
-    const int rd = fast_div(u, a.inv_half_w);  // row * N + image
-    const int px = u - rd * hw;
-    const int r = fast_div(rd, a.inv_n);
-    const int d = rd - r * a.N;
-    const int64_t y = y_first + r, x = x0 + 2 * px;
-    z0 = make_float2(0.f, 0.f);
-    z1 = z0;
-    if (y >= 0 && y < g.R) {
-        const float2* row = a.t.p[d] + y * g.C;
-        if (x >= 0 && x < g.C) z0 = row[x];
-        if (x + 1 >= 0 && x + 1 < g.C) z1 = row[x + 1];
-    }
-}
-
+// Row staging.  An "item" is one image and one pixel pair (x0 + 2 px, +1) of
+// the strip; a thread owns the items threadIdx.x + k * nthreads for the whole
+// kernel, so staging a row costs no index arithmetic beyond a row offset.  A
+// "unit" is one item in one row.
 // Ring slot of input row y (y may be negative above the image).
 __device__ __forceinline__ int ring_slot(int64_t y, int wy) {
     int s = (int)(y % wy);
     return s + (s < 0 ? wy : 0);
 }
 
-template <bool SPLIT>
-__device__ __forceinline__ void store_unit(const CohArgs& a, void* lds, int slot_first, int u,
-                                           float2 z0, float2 z1) {
-    const Geometry& g = a.g;
-    const int hw = a.tile_w >> 1;
-    const int rd = fast_div(u, a.inv_half_w);
-    const int px = u - rd * hw;
-    const int r = fast_div(rd, a.inv_n);
-    const int d = rd - r * a.N;
-    int slot = slot_first + r;  // r < 2 wy
-    slot -= slot >= g.wy ? g.wy : 0;
-    slot -= slot >= g.wy ? g.wy : 0;
-    const int e = slot * a.pitch + 2 * px;  // element offset inside a plane (even)
-    if constexpr (SPLIT) {
-        uint32_t* L = reinterpret_cast<uint32_t*>(lds);
-        const uint32_t rh0 = bf16_bits(z0.x), rh1 = bf16_bits(z1.x);
-        const uint32_t ih0 = bf16_bits(z0.y), ih1 = bf16_bits(z1.y);
-        const uint32_t rl0 = bf16_bits(z0.x - bf16_value(rh0)), rl1 = bf16_bits(z1.x - bf16_value(rh1));
-        const uint32_t il0 = bf16_bits(z0.y - bf16_value(ih0)), il1 = bf16_bits(z1.y - bf16_value(ih1));
-        const int hp = a.plane >> 1, w = e >> 1;
-        L[(0 * a.N + d) * hp + w] = rh0 | (rh1 << 16);
-        L[(1 * a.N + d) * hp + w] = rl0 | (rl1 << 16);
-        L[(2 * a.N + d) * hp + w] = ih0 | (ih1 << 16);
-        L[(3 * a.N + d) * hp + w] = il0 | (il1 << 16);
-    } else {
-        float* L = reinterpret_cast<float*>(lds);
-        L[(0 * a.N + d) * a.plane + e] = z0.x;
-        L[(0 * a.N + d) * a.plane + e + 1] = z1.x;
-        L[(1 * a.N + d) * a.plane + e] = z0.y;
-        L[(1 * a.N + d) * a.plane + e + 1] = z1.y;
+constexpr int kMaxItems = 8;
+
+struct Items {
+    int n;                     // items of this thread
+    uint32_t dp[kMaxItems];    // image << 16 | pair
+};
+
+__device__ __forceinline__ Items make_items(const CohArgs& a, int nthreads) {
+    Items it;
+    it.n = 0;
+    const int hw = a.tile_w >> 1, total = a.N * hw;
+#pragma unroll
+    for (int k = 0; k < kMaxItems; ++k) {
+        const int idx = threadIdx.x + k * nthreads;
+        it.dp[k] = 0;
+        if (idx < total) {
+            const int d = idx / hw;
+            it.dp[k] = ((uint32_t)d << 16) | (uint32_t)(idx - d * hw);
+            it.n = k + 1;
+        }
     }
+    return it;
 }
+
+// Units a thread keeps in registers while the current row is computed: its
+// first kPfItems items in the first kPfRows new rows (static indices, so they
+// stay in registers); any other unit is staged directly at commit time.
+constexpr int kPfItems = 2;
+template <int NT>
+constexpr int kPfRows = NT == 16 ? 4 : 2;
+
+template <int NT>
+struct RowLoad {
+    f32x4 v[kPfRows<NT>][kPfItems];
+};
+
+__device__ __forceinline__ f32x4 fetch_unit(const CohArgs& a, uint32_t dp, int64_t y, int64_t x0) {
+    const Geometry& g = a.g;
+    const int d = (int)(dp >> 16), px = (int)(dp & 0xffffu);
+    const int64_t x = x0 + 2 * px;
+    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    if (y >= 0 && y < g.R) {
+        const float2* row = a.t.p[d] + y * g.C;
+        if (a.vec_rows && x >= 0 && x + 1 < g.C) {
+            z = *reinterpret_cast<const f32x4*>(row + x);  // 16-byte aligned pair
+        } else {
+            if (x >= 0 && x < g.C) {
+                z[0] = row[x].x;
+                z[1] = row[x].y;
+            }
+            if (x + 1 >= 0 && x + 1 < g.C) {
+                z[2] = row[x + 1].x;
+                z[3] = row[x + 1].y;
+            }
+        }
+    }
+    return z;
+}
+
+// Converts a pixel pair {re0, im0, re1, im1} into its 16-byte record and
+// stores it in ring slot `slot`.
+template <bool SPLIT>
+__device__ __forceinline__ void store_unit(const CohArgs& a, void* lds, uint32_t dp, int slot, f32x4 z) {
+    const int d = (int)(dp >> 16), px = (int)(dp & 0xffffu);
+    u32x4* rec = reinterpret_cast<u32x4*>(lds) + d * a.plane + slot * a.pitch + px;
+    u32x4 v;
+    if constexpr (SPLIT) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        const f32x2 re = {z[0], z[2]}, im = {z[1], z[3]};
+        const bf16x2 rh = __builtin_convertvector(re, bf16x2);  // round to nearest even
+        const bf16x2 ih = __builtin_convertvector(im, bf16x2);
+        const bf16x2 rl = __builtin_convertvector(re - __builtin_convertvector(rh, f32x2), bf16x2);
+        const bf16x2 il = __builtin_convertvector(im - __builtin_convertvector(ih, f32x2), bf16x2);
+        v[0] = __builtin_bit_cast(uint32_t, rh);
+        v[1] = __builtin_bit_cast(uint32_t, rl);
+        v[2] = __builtin_bit_cast(uint32_t, ih);
+        v[3] = __builtin_bit_cast(uint32_t, il);
+    } else {
+        v = __builtin_bit_cast(u32x4, z);
+    }
+    *rec = v;
+}
+
+__device__ __forceinline__ int next_slot(int s, int wy) { return s + 1 == wy ? 0 : s + 1; }
 
 // Synchronous staging of rows [y_first, y_first + nrows).
 template <bool SPLIT>
-__device__ void load_rows(const CohArgs& a, void* lds, int64_t y_first, int nrows, int64_t x0,
-                          int nthreads) {
-    const int total = nrows * a.N * (a.tile_w >> 1);
-    const int sf = ring_slot(y_first, a.g.wy);
-    for (int u = threadIdx.x; u < total; u += nthreads) {
-        float2 z0, z1;
-        fetch_unit(a, y_first, x0, u, z0, z1);
-        store_unit<SPLIT>(a, lds, sf, u, z0, z1);
+__device__ void load_rows(const CohArgs& a, const Items& it, void* lds, int64_t y_first, int nrows,
+                          int64_t x0) {
+    int slot = ring_slot(y_first, a.g.wy);
+    for (int r = 0; r < nrows; ++r) {
+#pragma unroll
+        for (int k = 0; k < kMaxItems; ++k)
+            if (k < it.n) store_unit<SPLIT>(a, lds, it.dp[k], slot, fetch_unit(a, it.dp[k], y_first + r, x0));
+        slot = next_slot(slot, a.g.wy);
     }
 }
 
-// Start the global loads of the first kPrefetchUnits units of each thread;
-// they complete while the current row's pixels are computed.
+// Start the global loads of the prefetched units of the next rows; they
+// complete while the current row's pixels are computed.
 template <int NT>
-__device__ __forceinline__ void prefetch_rows(const CohArgs& a, RowLoad<NT>& pf, int64_t y_first,
-                                              int nrows, int64_t x0, int nthreads) {
-    const int total = nrows * a.N * (a.tile_w >> 1);
+__device__ __forceinline__ void prefetch_rows(const CohArgs& a, const Items& it, RowLoad<NT>& pf,
+                                              int64_t y_first, int nrows, int64_t x0) {
 #pragma unroll
-    for (int k = 0; k < kPrefetchUnits<NT>; ++k) {
-        const int u = threadIdx.x + k * nthreads;
-        if (u < total) fetch_unit(a, y_first, x0, u, pf.v[2 * k], pf.v[2 * k + 1]);
-    }
+    for (int r = 0; r < kPfRows<NT>; ++r)
+#pragma unroll
+        for (int k = 0; k < kPfItems; ++k)
+            if (r < nrows && k < it.n) pf.v[r][k] = fetch_unit(a, it.dp[k], y_first + r, x0);
 }
 
 template <int NT, bool SPLIT>
-__device__ __forceinline__ void commit_rows(const CohArgs& a, void* lds, const RowLoad<NT>& pf,
-                                            int64_t y_first, int nrows, int64_t x0, int nthreads) {
-    const int total = nrows * a.N * (a.tile_w >> 1);
-    const int sf = ring_slot(y_first, a.g.wy);
+__device__ __forceinline__ void commit_rows(const CohArgs& a, const Items& it, void* lds,
+                                            const RowLoad<NT>& pf, int64_t y_first, int nrows,
+                                            int64_t x0) {
+    const int s0 = ring_slot(y_first, a.g.wy);
+    int slot = s0;
 #pragma unroll
-    for (int k = 0; k < kPrefetchUnits<NT>; ++k) {
-        const int u = threadIdx.x + k * nthreads;
-        if (u < total) store_unit<SPLIT>(a, lds, sf, u, pf.v[2 * k], pf.v[2 * k + 1]);
+    for (int r = 0; r < kPfRows<NT>; ++r) {
+        if (r < nrows) {
+#pragma unroll
+            for (int k = 0; k < kPfItems; ++k)
+                if (k < it.n) store_unit<SPLIT>(a, lds, it.dp[k], slot, pf.v[r][k]);
+            slot = next_slot(slot, a.g.wy);
+        }
     }
-    // units beyond the register budget (very wide strips) are staged directly
-    for (int u = threadIdx.x + kPrefetchUnits<NT> * nthreads; u < total; u += nthreads) {
-        float2 z0, z1;
-        fetch_unit(a, y_first, x0, u, z0, z1);
-        store_unit<SPLIT>(a, lds, sf, u, z0, z1);
+    // units outside the prefetch grid
+    slot = s0;
+    for (int r = 0; r < nrows; ++r) {
+#pragma unroll
+        for (int k = 0; k < kMaxItems; ++k)
+            if (k < it.n && (k >= kPfItems || r >= kPfRows<NT>))
+                store_unit<SPLIT>(a, lds, it.dp[k], slot, fetch_unit(a, it.dp[k], y_first + r, x0));
+        slot = next_slot(slot, a.g.wy);
     }
 }
 
-// List the window pairs of output pixel (oy, ox) that hold an SHP.  Entry =
-// (element offset << 2) | (bit0 | bit1 << 1), padded with zero entries to a
-// multiple of `ppk`.  `mw` holds mask word `lane` of the pixel (lanes < nw);
-// `s0` is the ring slot of the window's first row.  Returns the padded count
-// (uniform over the wave).
+// List the window pairs of output pixel (oy, ox) that hold an SHP as entries
+// of two words: the record offset inside an image plane and a mask word
+// (SPLIT: 0xffff per selected BF16 half; FP32: bit 0 / bit 1 for the first /
+// second pixel).  The list is padded with zero entries to a multiple of
+// `ppk`.  `mw` holds mask word `lane` of the pixel (lanes < nw); `s0` is the
+// ring slot of the window's first row.  Returns the padded count (uniform
+// over the wave).
+template <bool SPLIT>
 __device__ int build_pairs(const CohArgs& a, uint32_t* table, int64_t ox, int64_t x0, int s0,
                            uint32_t mw, int ppk, int lane) {
     const Geometry& g = a.g;
     const int64_t cx = ox * g.sx + g.sx / 2;
     const int rel = (int)(cx - g.hx - x0);  // >= 0 by construction of x0
-    const int xs = rel & ~1, par = rel & 1;
+    const int rec0 = rel >> 1, par = rel & 1;
     const int ppr = g.hx + 1;  // pairs per window row
     int n = 0;
     for (int base = 0; base < a.n_pairs; base += 64) {
@@ -240,11 +282,19 @@ __device__ int build_pairs(const CohArgs& a, uint32_t* table, int64_t ox, int64_
         const bool keep = bits != 0;
         const uint64_t bal = __ballot(keep);
         const int before = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-        if (keep) table[n + before] = ((uint32_t)(slot * a.pitch + xs + 2 * px) << 2) | bits;
+        if (keep) {
+            uint32_t mword = bits;
+            if constexpr (SPLIT) mword = ((bits & 1u) ? 0x0000ffffu : 0u) | ((bits & 2u) ? 0xffff0000u : 0u);
+            table[2 * (n + before)] = (uint32_t)(slot * a.pitch + rec0 + px);
+            table[2 * (n + before) + 1] = mword;
+        }
         n += __popcll(bal);
     }
     const int npad = (n + ppk - 1) / ppk * ppk;
-    for (int j = n + lane; j < npad; j += 64) table[j] = 0u;
+    for (int j = n + lane; j < npad; j += 64) {
+        table[2 * j] = 0u;
+        table[2 * j + 1] = 0u;
+    }
     return npad;
 }
 
@@ -299,53 +349,31 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
     const int d = lane & (NT - 1);
     const bool live = d < a.N;
     const int g = lane / NT;  // k-group of this lane
+    // Dead rows (image index >= N) read a valid plane and are masked to zero
+    // on the A side; their garbage B columns are never stored.
+    const int dd = live ? d : a.N - 1;
+    const uint32_t live_mask = live ? 0xffffffffu : 0u;
     AT whh = {}, v1 = {};
     if constexpr (SPLIT) {
         AT whl = {}, v2 = {};
         constexpr int PPK = NT == 16 ? 16 : 8;  // pairs per k-step
-        const uint32_t* L = reinterpret_cast<const uint32_t*>(lds);
-        const int half_plane = a.plane >> 1;  // plane stride in 32-bit words
-        const int dd = live ? d : a.N - 1;
-        const uint32_t* prh = L + (0 * a.N + dd) * half_plane;
-        const uint32_t* prl = L + (1 * a.N + dd) * half_plane;
-        const uint32_t* pih = L + (2 * a.N + dd) * half_plane;
-        const uint32_t* pil = L + (3 * a.N + dd) * half_plane;
-        // Dead rows (image index >= N) read a valid plane and are masked to
-        // zero on the A side; their garbage B columns are never stored.
-        const uint32_t live_mask = live ? 0xffffffffu : 0u;
-        // software pipeline: the LDS reads of step ks + PPK are issued before
-        // the MFMAs of step ks
-        u32x4 e = *reinterpret_cast<const u32x4*>(table + 4 * g);
-        u32x4 rh, rl, ih, il;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const uint32_t off = e[t] >> 3;  // element offset / 2 = word offset
-            rh[t] = prh[off];
-            rl[t] = prl[off];
-            ih[t] = pih[off];
-            il[t] = pil[off];
-        }
+        const u32x4* P = reinterpret_cast<const u32x4*>(lds) + dd * a.plane;
+        const u32x4* E = reinterpret_cast<const u32x4*>(table) + 2 * g;  // 4 entries per group
+        // the entries of the next k-step are read one step ahead
+        u32x4 e01 = E[0], e23 = E[1];
         for (int ks = 0; ks < npad; ks += PPK) {
-            u32x4 en = e, nrh = rh, nrl = rl, nih = ih, nil = il;
+            const u32x4 q0 = P[e01[0]], q1 = P[e01[2]], q2 = P[e23[0]], q3 = P[e23[2]];
+            u32x4 n01 = e01, n23 = e23;
             if (ks + PPK < npad) {
-                en = *reinterpret_cast<const u32x4*>(table + ks + PPK + 4 * g);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const uint32_t off = en[t] >> 3;
-                    nrh[t] = prh[off];
-                    nrl[t] = prl[off];
-                    nih[t] = pih[off];
-                    nil[t] = pil[off];
-                }
+                n01 = E[(ks + PPK) / 2];
+                n23 = E[(ks + PPK) / 2 + 1];
             }
-            u32x4 rhm, ihm;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t bits = e[t] & 3u;
-                const uint32_t msk = (((bits & 1u) ? 0x0000ffffu : 0u) | ((bits & 2u) ? 0xffff0000u : 0u)) & live_mask;
-                rhm[t] = rh[t] & msk;
-                ihm[t] = ih[t] & msk;
-            }
+            const uint32_t m0 = e01[1] & live_mask, m1 = e01[3] & live_mask;
+            const uint32_t m2 = e23[1] & live_mask, m3 = e23[3] & live_mask;
+            const u32x4 rh = {q0[0], q1[0], q2[0], q3[0]}, rl = {q0[1], q1[1], q2[1], q3[1]};
+            const u32x4 ih = {q0[2], q1[2], q2[2], q3[2]}, il = {q0[3], q1[3], q2[3], q3[3]};
+            const u32x4 rhm = {q0[0] & m0, q1[0] & m1, q2[0] & m2, q3[0] & m3};
+            const u32x4 ihm = {q0[2] & m0, q1[2] & m1, q2[2] & m2, q3[2] & m3};
             const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh), Rl = __builtin_bit_cast(bf16x8, rl);
             const bf16x8 Ih = __builtin_bit_cast(bf16x8, ih), Il = __builtin_bit_cast(bf16x8, il);
             const bf16x8 Rm = __builtin_bit_cast(bf16x8, rhm), Im = __builtin_bit_cast(bf16x8, ihm);
@@ -368,11 +396,8 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
                 whl = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Im, Il, whl, 0, 0, 0);
                 v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rm, Il, v1, 0, 0, 0);
             }
-            e = en;
-            rh = nrh;
-            rl = nrl;
-            ih = nih;
-            il = nil;
+            e01 = n01;
+            e23 = n23;
         }
         AT t;
         transpose_read<NT>(S, whl, t, lane);
@@ -382,17 +407,16 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
         im = u - t;
     } else {
         constexpr int SPK = NT == 16 ? 4 : 2;  // samples per k-step
-        const float* L = reinterpret_cast<const float*>(lds);
-        const int dd = live ? d : a.N - 1;
-        const float* pr = L + (0 * a.N + dd) * a.plane;
-        const float* pi = L + (1 * a.N + dd) * a.plane;
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        const f32x2* P = reinterpret_cast<const f32x2*>(lds) + 2 * dd * a.plane;
         const int half = g & 1;
         const int eoff = g >> 1;  // which pair of the k-step (16x16x4 only)
         for (int ks = 0; ks < npad; ks += SPK / 2) {
-            const uint32_t e = table[ks + eoff];
-            const uint32_t off = (e >> 2) + half;
-            const bool on = live && ((e >> half) & 1u);
-            const float r = pr[off], im_ = pi[off];
+            const u32x2 e = *reinterpret_cast<const u32x2*>(table + 2 * (ks + eoff));
+            const f32x2 z = P[2 * e[0] + half];  // {re, im} of this lane's sample
+            const bool on = live && ((e[1] >> half) & 1u);
+            const float r = z[0], im_ = z[1];
             const float rm = on ? r : 0.f, imm = on ? im_ : 0.f;
             if constexpr (NT == 16) {
                 whh = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, r, whh, 0, 0, 0);
@@ -412,7 +436,7 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
 }
 
 template <int NT, bool SPLIT>
-__global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
+__global__ __launch_bounds__(64 * kMaxWaves) void coherence_kernel(CohArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
     const Geometry& g = a.g;
     const int nthreads = blockDim.x;
@@ -425,7 +449,7 @@ __global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
     const int64_t oy0 = (int64_t)blockIdx.y * a.rows_per_wg;
     const int64_t oy1 = oy0 + a.rows_per_wg < g.oR ? oy0 + a.rows_per_wg : g.oR;
     const int64_t x0 = (ox0 * g.sx + g.sx / 2 - g.hx) & ~(int64_t)1;
-    const int data_words = 2 * a.N * a.plane;  // 8 bytes per image per element
+    const int data_words = 4 * a.N * a.plane;  // one 16-byte record per pixel pair
     uint32_t* wave_area = lds_words + data_words + wave * a.wave_words;
     float* S = reinterpret_cast<float*>(wave_area);
     constexpr int PPK = SPLIT ? (NT == 16 ? 16 : 8) : (NT == 16 ? 2 : 1);
@@ -436,8 +460,9 @@ __global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
         return s0 + (s0 < 0 ? g.wy : 0);
     };
     RowLoad<NT> pf;
+    const Items items = make_items(a, nthreads);
     // prologue: the full window of the first output row
-    load_rows<SPLIT>(a, lds_words, oy0 * g.sy + g.sy / 2 - g.hy, g.wy, x0, nthreads);
+    load_rows<SPLIT>(a, items, lds_words, oy0 * g.sy + g.sy / 2 - g.hy, g.wy, x0);
     __syncthreads();
     for (int64_t oy = oy0; oy < oy1; ++oy) {
         const int64_t cy = oy * g.sy + g.sy / 2;
@@ -445,7 +470,7 @@ __global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
         const int64_t next_first = (cy + g.hy + 1) > (cy + g.sy - g.hy) ? (cy + g.hy + 1) : (cy + g.sy - g.hy);
         const int next_rows = (int)((cy + g.sy + g.hy) - next_first + 1);
         const bool more = oy + 1 < oy1;
-        if (more) prefetch_rows<NT>(a, pf, next_first, next_rows, x0, nthreads);
+        if (more) prefetch_rows<NT>(a, items, pf, next_first, next_rows, x0);
         const int s0 = first_slot(oy);
         int64_t ox = ox0 + wave;
         uint32_t mw = 0;
@@ -453,7 +478,7 @@ __global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
         for (; ox < ox1; ox += nwaves) {
             const uint32_t mcur = mw;
             if (ox + nwaves < ox1 && lane < g.nw) mw = a.mask[(oy * g.oC + ox + nwaves) * g.nw + lane];
-            const int npad = build_pairs(a, wave_area, ox, x0, s0, mcur, PPK, lane);
+            const int npad = build_pairs<SPLIT>(a, wave_area, ox, x0, s0, mcur, PPK, lane);
             wave_sync();
             typename Acc<NT>::T re, im;
             pixel_gram<NT, SPLIT>(a, lds_words, wave_area, npad, lane, re, im, S);
@@ -461,7 +486,7 @@ __global__ __launch_bounds__(512) void coherence_kernel(CohArgs a) {
         }
         __syncthreads();  // every wave is done with the rows about to be replaced
         if (more) {
-            commit_rows<NT, SPLIT>(a, lds_words, pf, next_first, next_rows, x0, nthreads);
+            commit_rows<NT, SPLIT>(a, items, lds_words, pf, next_first, next_rows, x0);
             __syncthreads();
         }
     }
@@ -474,22 +499,18 @@ pl_status launch_variant(const CohArgs& a0, hipStream_t s) {
     const size_t lds_cap = max_lds_bytes();
     constexpr int PPK = SPLIT ? (NT == 16 ? 16 : 8) : (NT == 16 ? 2 : 1);
     const int scratch_words = NT * (NT + 1) + NT;
-    const int table_words = ((a.n_pairs + PPK + 3) / 4) * 4;
+    const int table_words = ((2 * (a.n_pairs + PPK) + 3) / 4) * 4;
     a.wave_words = ((scratch_words > table_words ? scratch_words : table_words) + 3) / 4 * 4;
     int chosen = 0;
     size_t lds = 0;
     for (int txo = 16; txo >= 1; --txo) {
         int tile_w = (txo - 1) * g.sx + 2 * g.hx + 3;
         tile_w += tile_w & 1;
-        int pitch = tile_w;
+        const int pitch = tile_w >> 1;
         int plane = g.wy * pitch;
-        if (SPLIT) {
-            if (((plane >> 1) & 1) == 0) plane += 2;  // odd word stride between planes
-        } else {
-            if ((plane & 1) == 0) plane += 1;
-        }
-        int nw = txo < kMaxWaves ? txo : kMaxWaves;
-        size_t bytes = (size_t)8 * a.N * plane + (size_t)nw * a.wave_words * 4;
+        plane += (1 - plane % 16 + 16) % 16;  // records = 1 mod 16: stride 4 mod 64 words
+        const int nw = txo < kMaxWaves ? txo : kMaxWaves;
+        const size_t bytes = (size_t)16 * a.N * plane + (size_t)nw * a.wave_words * 4;
         if (bytes <= lds_cap) {
             chosen = txo;
             a.tile_w = tile_w;
@@ -501,10 +522,13 @@ pl_status launch_variant(const CohArgs& a0, hipStream_t s) {
     }
     if (!chosen) return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: window too large for LDS");
     a.TXo = chosen;
-    a.inv_half_w = 1.0f / (float)(a.tile_w >> 1);
-    a.inv_n = 1.0f / (float)a.N;
     a.inv_ppr = 1.0f / (float)(g.hx + 1);
     const int nwaves = chosen < kMaxWaves ? chosen : kMaxWaves;
+    if ((int64_t)a.N * (a.tile_w >> 1) > (int64_t)kMaxItems * 64 * nwaves)
+        return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: strip too wide for the staging layout");
+    a.vec_rows = (g.C % 2) == 0;
+    for (int d = 0; d < a.N; ++d)
+        if (reinterpret_cast<uintptr_t>(a.t.p[d]) & 15) a.vec_rows = 0;
     const int64_t n_strips = (g.oC + chosen - 1) / chosen;
     // enough workgroups to fill the chip several times over
     int64_t rows = (g.oR * n_strips + 2047) / 2048;

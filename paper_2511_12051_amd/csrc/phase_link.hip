@@ -172,6 +172,20 @@ __device__ __forceinline__ float2 matvec(const float2 (&m)[NP], float2 x, int i,
     return y;
 }
 
+// y_i = sum_j B_ij x_j with this lane's row of B in LDS (stride kBlock).
+template <int NP>
+__device__ __forceinline__ float2 matvec_lds(const float2* brow, float2 x, int i, float2* xb) {
+    xb[i] = x;
+    float2 y = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const float2 v = xb[j], m = brow[j * kBlock];
+        y.x = fmaf(m.x, v.x, fmaf(-m.y, v.y, y.x));
+        y.y = fmaf(m.x, v.y, fmaf(m.y, v.x, y.y));
+    }
+    return y;
+}
+
 template <int NP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
 void phase_link_kernel(LinkArgs a) {
@@ -181,6 +195,10 @@ void phase_link_kernel(LinkArgs a) {
     constexpr int ROW_BYTES = (NP + 2) * 8;
     constexpr int GROUP_BYTES = 2 * ROW_BYTES + NP * 8;
     __shared__ __attribute__((aligned(16))) unsigned char lds[(kBlock / 64) * GPW * GROUP_BYTES];
+    // row i of B for every lane, element-major so that the lanes of a
+    // wavefront read consecutive words: read back for refactorisations and
+    // Rayleigh quotients instead of occupying registers through the iteration
+    __shared__ __attribute__((aligned(16))) float2 brow[NP][kBlock];
     const int lane = lane_id();
     const int i = lane & (NP - 1);
     const int grp = lane / NP;
@@ -277,11 +295,15 @@ void phase_link_kernel(LinkArgs a) {
             c[j] = make_float2(v.x, v.y);
         }
     }
-    float2 b[NP];
+    float2* bme = &brow[0][threadIdx.x];  // element j at bme[j * kBlock]
+    float bnorm2 = 0.f;  // ||row i of B||^2
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-        if (use_evd) b[j] = make_float2(-c[j].x, -c[j].y);
-        else b[j] = make_float2((float)gi[j] * c[j].x, (float)gi[j] * c[j].y);
+        float2 v;
+        if (use_evd) v = make_float2(-c[j].x, -c[j].y);
+        else v = make_float2((float)gi[j] * c[j].x, (float)gi[j] * c[j].y);
+        bme[j * kBlock] = v;
+        bnorm2 += v.x * v.x + v.y * v.y;
     }
     float mu = use_evd ? evd_shift : 0.99f;
 
@@ -303,7 +325,7 @@ void phase_link_kernel(LinkArgs a) {
     for (int guard = 0; guard < 2 * kMaxIter; ++guard) {
         if (gany<64>(need, 0)) {
 #pragma unroll
-            for (int j = 0; j < NP; ++j) if (need) m[j] = b[j];
+            for (int j = 0; j < NP; ++j) if (need) m[j] = bme[j * kBlock];
             const bool ok = invert_c<NP>(m, mu_req, N, i, need, rbc0, rbc1);
             if (need) {
                 if (ok) {
@@ -330,10 +352,7 @@ void phase_link_kernel(LinkArgs a) {
                     if (stage == 1) mu_req = 0.5f;
                     else if (stage == 2) mu_req = 0.0f;
                     else if (stage == 3) {
-                        float fr = 0.f;
-#pragma unroll
-                        for (int j = 0; j < NP; ++j) fr += b[j].x * b[j].x + b[j].y * b[j].y;
-                        mu_req = -sqrtf(gsum<NP>(fr)) - 1.0f;  // below -||B||_F <= lambda_min
+                        mu_req = -sqrtf(gsum<NP>(bnorm2)) - 1.0f;  // below -||B||_F <= lambda_min
                     } else {
                         need = false;
                         conv = true;
@@ -367,7 +386,7 @@ void phase_link_kernel(LinkArgs a) {
             // rejects it.
             const bool slow = !conv && q2 > kRefineRate * kRefineRate;
             if (gany<64>(slow, 0)) {
-                const float2 bx = matvec<NP>(b, x, i, xb);
+                const float2 bx = matvec_lds<NP>(bme, x, i, xb);
                 const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
                 const float rx = bx.x - rho * x.x, ry = bx.y - rho * x.y;
                 const float res = sqrtf(gsum<NP>(rx * rx + ry * ry));
@@ -384,7 +403,7 @@ void phase_link_kernel(LinkArgs a) {
     }
 
     // ---- 4. eigenvalue, reference and unit phasors
-    const float2 bx = matvec<NP>(b, x, i, xb);
+    const float2 bx = matvec_lds<NP>(bme, x, i, xb);
     const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
     const float2 xr = make_float2(__shfl(x.x, grp * NP + a.ref, 64), __shfl(x.y, grp * NP + a.ref, 64));
     float2 z = make_float2(x.x * xr.x + x.y * xr.y, x.y * xr.x - x.x * xr.y);  // x conj(x_ref)
