@@ -344,6 +344,104 @@ def phase_sensitivity(Cmat, ref=0, method="emi", n_probe=4, eps=1e-7, seed=0):
 
 
 # --------------------------------------------------------------------------
+# adjoint of coherence + phase linking (test oracle for the GPU adjoint)
+# --------------------------------------------------------------------------
+def link_phases_fixed(stack, mask, window, ref, flags, pixels=None):
+    """Linked phases [N, P] with the SHP mask and the EMI/EVD choice held
+    fixed (flags from an earlier phase_link) - the function the adjoint
+    differentiates."""
+    Cm, valid = coherence(stack, mask, window, pixels=pixels)
+    emi = np.asarray(flags) == FLAG_EMI
+    out = np.zeros((Cm.shape[1], Cm.shape[0]))
+    if emi.any():
+        out[:, emi] = phase_link(Cm[emi], ref=ref, method="emi", tau=-np.inf)["phase"]
+    evd = np.asarray(flags) == FLAG_EVD
+    if evd.any():
+        out[:, evd] = phase_link(Cm[evd], ref=ref, method="evd")["phase"]
+    return out
+
+
+def phase_link_vjp(stack, mask, window, ref, grad_phase, flags):
+    """Vector-Jacobian product of the linked phases with respect to the stack.
+
+    grad_phase [N, P] is dL/dphi for every output pixel; returns dL/dz as a
+    complex128 [N, R, C] array in the convention dL/dRe + j dL/dIm.  The SHP
+    mask and the EMI/EVD choice (flags) are held fixed, invalid pixels
+    contribute nothing.  Per pixel, with A = sum z z^H over the SHPs,
+    C = D^-1/2 A D^-1/2, G = |C|, H = G^-1 o C (EMI) or H = -C (EVD) and v
+    the eigenvector of the smallest eigenvalue lambda of H:
+      phi_i = arg(v_i conj(v_r))       -> dL = Re(u^H dv)
+      dv = -(H - lambda I)^+ dH v      -> Hbar = -y v^H, y = (H - lambda I)^+ u
+      dH = -(G^-1 dG G^-1) o C + G^-1 o dC, dG = Re(conj(C) dC)/|C|
+      C = A / sqrt(A_mm A_nn),  A = sum z z^H  -> grad z_q = (Abar + Abar^H) z_q.
+    """
+    z = np.asarray(stack).astype(np.complex128)
+    N, R, Cc = z.shape
+    cy, cx = output_centres(R, Cc, window)
+    oR, oC = len(cy), len(cx)
+    P = oR * oC
+    offs = window_offsets(window)
+    bits = mask_bits(np.asarray(mask).reshape(P, -1), window)
+    oy, ox = np.meshgrid(np.arange(oR), np.arange(oC), indexing="ij")
+    oy, ox = oy.ravel(), ox.ravel()
+    A = np.zeros((P, N, N), dtype=np.complex128)
+    for b, (dy, dx) in enumerate(offs):
+        qy, qx = cy[oy] + dy, cx[ox] + dx
+        use = bits[:, b] & (qy >= 0) & (qy < R) & (qx >= 0) & (qx < Cc)
+        zq = np.where(use[:, None], z[:, np.clip(qy, 0, R - 1), np.clip(qx, 0, Cc - 1)].T, 0)
+        A += zq[:, :, None] * np.conj(zq[:, None, :])
+    d = np.real(np.einsum("pii->pi", A))
+    flags = np.asarray(flags)
+    grad = np.zeros_like(z)
+    g = np.asarray(grad_phase, dtype=np.float64).reshape(N, P)
+    S = np.zeros((P, N, N), dtype=np.complex128)
+    for p in range(P):
+        if flags[p] == FLAG_INVALID or not np.all(d[p] > 0):
+            continue
+        s = np.sqrt(np.outer(d[p], d[p]))
+        Cp = A[p] / s
+        if flags[p] == FLAG_EMI:
+            G = np.abs(Cp)
+            Gi = np.linalg.inv(G)
+            H = Gi * Cp
+        else:
+            H = -Cp
+        H = 0.5 * (H + H.conj().T)
+        w, V = np.linalg.eigh(H)
+        v, lam = V[:, 0], w[0]
+        # dL = sum_i g_i Im(dv_i/v_i) - (sum_i g_i) Im(dv_r/v_r) = Im(wv^T dv)
+        wv = np.zeros(N, dtype=np.complex128)
+        for i in range(N):
+            if i != ref:
+                wv[i] = g[i, p] / v[i]
+        wv[ref] = -(g[:, p].sum() - g[ref, p]) / v[ref]
+        u = 1j * np.conj(wv)  # Im(wv^T dv) = Re(u^H dv)
+        y = np.zeros(N, dtype=np.complex128)  # (H - lam I)^+ u
+        for k in range(1, N):
+            y += V[:, k] * (np.vdot(V[:, k], u) / (w[k] - lam))
+        Hbar = -np.outer(y, np.conj(v))
+        Hbar = 0.5 * (Hbar + Hbar.conj().T)  # dH is Hermitian
+        if flags[p] == FLAG_EMI:
+            Kbar = np.real(np.conj(Hbar) * Cp)
+            Gbar = -Gi @ Kbar @ Gi
+            with np.errstate(all="ignore"):
+                unit = np.where(G > 0, Cp / G, 0)
+            Cbar = Hbar * Gi + Gbar * unit
+        else:
+            Cbar = -Hbar
+        Abar = Cbar / s
+        t = np.real(np.conj(Cbar) * Cp)
+        Abar[np.arange(N), np.arange(N)] -= 0.5 * (t.sum(axis=1) + t.sum(axis=0)) / d[p]
+        S[p] = Abar + Abar.conj().T
+    for b, (dy, dx) in enumerate(offs):
+        qy, qx = cy[oy] + dy, cx[ox] + dx
+        use = bits[:, b] & (qy >= 0) & (qy < R) & (qx >= 0) & (qx < Cc)
+        for p in np.nonzero(use)[0]:
+            grad[:, qy[p], qx[p]] += S[p] @ z[:, qy[p], qx[p]]
+    return grad
+
+
+# --------------------------------------------------------------------------
 # compressed SLC (Sec. 2.2; reading R7)
 # --------------------------------------------------------------------------
 def compress(stack, first_real, phasors, window):

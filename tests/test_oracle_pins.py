@@ -386,3 +386,61 @@ def test_sequential_is_append_only():
     for x, y in zip(a2, a3[:2]):
         np.testing.assert_array_equal(x["phasor"], y["phasor"])
         np.testing.assert_array_equal(x["kappa"], y["kappa"])
+
+
+# ---------------------------------------------------------------- adjoint
+def _adjoint_case(seed, N=5, R=10, C=11, w=(2, 2, 3, 2)):
+    rng = np.random.default_rng(seed)
+    z = rng.normal(size=(N, R, C)) + 1j * rng.normal(size=(N, R, C))
+    z += 1.2 * (rng.normal(size=(1, R, C)) + 1j * rng.normal(size=(1, R, C)))
+    z *= np.exp(1j * rng.uniform(-3, 3, (N, 1, 1)))
+    mean, var = O.amplitude_stats(z)
+    mask, _, _ = O.shp_select(mean, var, N, w, 0.3)
+    Cm, valid = O.coherence(z, mask, w)
+    flags = O.phase_link(Cm, ref=1, valid=valid)["flag"]
+    g = rng.normal(size=(N, len(flags)))
+    return z, mask, w, flags, g
+
+
+@pytest.mark.parametrize("method", ["emi", "evd"])
+def test_adjoint_matches_central_finite_differences(method):
+    z, mask, w, flags, g = _adjoint_case(41)
+    if method == "evd":
+        flags = np.where(flags == O.FLAG_INVALID, flags, O.FLAG_EVD).astype(np.uint8)
+    assert np.any(flags == (O.FLAG_EMI if method == "emi" else O.FLAG_EVD))
+    ref = 1
+    grad = O.phase_link_vjp(z, mask, w, ref, g, flags)
+
+    def loss(zz):
+        ph = O.link_phases_fixed(zz, mask, w, ref, flags)
+        return float(np.sum(g * ph))
+
+    h = 1e-6
+    rng = np.random.default_rng(42)
+    N, R, C = z.shape
+    idx = [(int(rng.integers(N)), int(rng.integers(R)), int(rng.integers(C))) for _ in range(40)]
+    fd = np.zeros(len(idx), complex)
+    for k, (i, y, x) in enumerate(idx):
+        for part, unit in ((0, 1.0), (1, 1j)):
+            zp, zm = z.copy(), z.copy()
+            zp[i, y, x] += h * unit
+            zm[i, y, x] -= h * unit
+            dv = (loss(zp) - loss(zm)) / (2 * h)
+            fd[k] += dv if part == 0 else 1j * dv
+    an = np.array([grad[i, y, x] for (i, y, x) in idx])
+    assert np.linalg.norm(an - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_adjoint_phase_screen_closed_form():
+    """z_i -> z_i exp(j d_i) moves phi_i by d_i - d_ref exactly, so the VJP
+    contracted with dz = j d_i z_i equals sum_p sum_i g_i (d_i - d_ref)."""
+    z, mask, w, flags, g = _adjoint_case(43)
+    ref = 1
+    grad = O.phase_link_vjp(z, mask, w, ref, g, flags)
+    rng = np.random.default_rng(44)
+    d = rng.normal(size=z.shape[0])
+    dz = 1j * d[:, None, None] * z
+    lhs = np.real(np.sum(np.conj(grad) * dz))
+    ok = flags != O.FLAG_INVALID
+    rhs = np.sum(g[:, ok] * (d - d[ref])[:, None])
+    assert abs(lhs - rhs) <= 1e-9 * max(1.0, abs(rhs))
