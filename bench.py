@@ -148,6 +148,37 @@ def roofline(alg, t_ms):
     return r
 
 
+def kernel_name(stage, wl, prec):
+    """Device kernel that runs a stage (as rocprofv3 names it, without spaces)."""
+    tile = 16 if wl.N <= 16 else 32
+    return {"stats": "amp_stats_vec", "glrt": "glrt_kernel",
+            "coherence": f"coherence_kernel<{tile},{'true' if prec == 'bf16' else 'false'}>",
+            "link": f"phase_link_kernel<{tile}>", "compress": "compress_kernel"}[stage]
+
+
+def measured_traffic(kernel, wl, prec):
+    """HBM bytes per launch of a kernel from the FETCH_SIZE / WRITE_SIZE
+    summary under profiles/ (already scaled by the copy calibration), or None
+    when there is none for this workload or the kernel source has changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    for f in glob.glob(os.path.join(ROOT, "profiles", f"hbm_traffic_{wl.name}_*.txt")):
+        for line in open(f):
+            if not line.startswith("traffic "):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("kernel") != kernel or kv.get("precision") != prec:
+                continue
+            src = os.path.join(ROOT, "paper_2511_12051_amd", "csrc", kv["source"])
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha256"]:
+                return None
+            return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
+    return None
+
+
 def cpu_baseline(wl_name, seed):
     """The FP64 oracle on a bounded crop of the same workload (host cores)."""
     import numpy as np
@@ -204,11 +235,17 @@ def main():
         ms = time_steps(torch, path.step, args.steps, args.warmup)
         stages = stage_times(torch, path, max(3, args.steps // 2))
         m, coh, ln, k = path.step()
+        cnt = plink.new_counters()
+        plink.phase_link(coh, ref=path.ref, counters=cnt)
         torch.cuda.synchronize()
+        cnt = dict(zip(plink.COUNTERS, cnt.cpu().tolist()))
         shp_sum = int(m[1].to(torch.int32).sum().item())
         flags = ln[2].cpu().numpy()
         results[prec] = {"ms": ms, "stages": stages, "shp_sum": shp_sum,
-                         "evd_frac": float(np.mean(flags == 1)), "invalid_frac": float(np.mean(flags == 2))}
+                         "evd_frac": float(np.mean(flags == 1)), "invalid_frac": float(np.mean(flags == 2)),
+                         "link_counters": {"iters_per_pixel": cnt["iters"] / P,
+                                           "shift_retries_per_pixel": cnt["shift_retry"] / P,
+                                           "not_converged": cnt["not_converged"]}}
         print(f"[bench] {prec}: {ms:.3f} ms/step, stages {json.dumps({k: round(v, 4) for k, v in stages.items()})}",
               file=sys.stderr, flush=True)
 
@@ -217,8 +254,8 @@ def main():
     st = main_r["stages"]
     dom = max(st, key=st.get)
     roof = roofline(alg[dom], st[dom])
-    roof["traffic"] = None
-    roof["kernel"] = dom
+    roof["kernel"] = kernel_name(dom, wl, args.precision)
+    roof["traffic"] = measured_traffic(roof["kernel"], wl, args.precision)
     stage_roof = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                       for kk, vv in roofline(alg[k], st[k]).items()} for k in st}
 
@@ -251,6 +288,7 @@ def main():
             line["mixed_speedup_vs_fp32"] = (results["fp32"]["ms"] / results["bf16"]["ms"]
                                              if "fp32" in results and "bf16" in results else None)
     line["evd_fraction"] = main_r["evd_frac"]
+    line["link_counters"] = main_r["link_counters"]
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a crop (host cores)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.workload, args.seed)

@@ -186,141 +186,56 @@ __device__ __forceinline__ float2 matvec_lds(const float2* brow, float2 x, int i
     return y;
 }
 
+// In-place FP64 Gauss-Jordan inversion of G (row i = this lane's g[]) for
+// lanes with act; returns (per group) whether some pivot was <= 1e-6 or not
+// finite, i.e. the inversion failed.  Same publishing scheme as invert_c.
 template <int NP>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
-void phase_link_kernel(LinkArgs a) {
-    constexpr int GPW = 64 / NP;  // groups (pixels) per wavefront
-    // per group: two GJ pivot-row buffers (NP + 2 doubles each, also used as
-    // NP + 2 float2) and the iterate buffer (NP float2)
-    constexpr int ROW_BYTES = (NP + 2) * 8;
-    constexpr int GROUP_BYTES = 2 * ROW_BYTES + NP * 8;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[(kBlock / 64) * GPW * GROUP_BYTES];
-    // row i of B for every lane, element-major so that the lanes of a
-    // wavefront read consecutive words: read back for refactorisations and
-    // Rayleigh quotients instead of occupying registers through the iteration
-    __shared__ __attribute__((aligned(16))) float2 brow[NP][kBlock];
-    const int lane = lane_id();
-    const int i = lane & (NP - 1);
-    const int grp = lane / NP;
-    const int wave = threadIdx.x >> 6;
-    unsigned char* gbase = lds + (wave * GPW + grp) * GROUP_BYTES;
-    double* rbd0 = reinterpret_cast<double*>(gbase);
-    double* rbd1 = reinterpret_cast<double*>(gbase + ROW_BYTES);
-    float2* rbc0 = reinterpret_cast<float2*>(gbase);
-    float2* rbc1 = reinterpret_cast<float2*>(gbase + ROW_BYTES);
-    float2* xb = reinterpret_cast<float2*>(gbase + 2 * ROW_BYTES);
-
-    const int N = a.N;
-    const int64_t pix = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * GPW + grp;
-    const bool active = pix < a.npix;
-    const bool row_live = active && i < N;
-
-    // ---- load row i of C
-    float2 c[NP];
-    const float2* src = a.coh + (active ? pix : 0) * (int64_t)N * N + (int64_t)i * N;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
-    const bool invalid = !active || gany<NP>(bad, grp);
-
-    // start from column ref of C: the single-reference interferogram phases
-    float2 x = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-        if (j == a.ref && row_live) x = c[j];
-    {
-        float nrm = gsum<NP>(x.x * x.x + x.y * x.y);
-        if (!(nrm > 0.f)) {
-            x = make_float2(i == a.ref ? 1.f : 0.f, 0.f);
-            nrm = 1.f;
-        }
-        const float s = 1.0f / sqrtf(nrm);
-        x.x *= s;
-        x.y *= s;
-    }
-    // EVD shift: minus a Gershgorin bound on lambda_max(C), so -C - mu I > 0
-    float evd_shift;
-    {
-        float rs = 0.f;
-#pragma unroll
-        for (int j = 0; j < NP; ++j) rs += sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
-        evd_shift = -(1.0f + 1e-3f) * gmax<NP>(rs) - 1e-3f;
-    }
-
-    // ---- 1. FP64 inverse of G = |C|
-    bool use_evd = a.method == PL_LINK_EVD;
-    double gi[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        const double re = c[j].x, im = c[j].y;
-        gi[j] = (row_live && j < N) ? sqrt(fma(re, re, im * im)) : 0.0;
-    }
-    const bool do_emi = !use_evd && !invalid;
-    bool gfail = false;
-    if (gany<64>(do_emi, 0)) {
-        // same scheme as invert_c: the owner of row k+1 publishes it after
-        // its step-k update, double-buffered
-        if (do_emi && i == 0) publish_d<NP>(gi, 0, rbd0);
+__device__ bool invert_g(double (&g)[NP], int N, int i, bool act, double* rbd0, double* rbd1) {
+    bool fail = false;
+    if (!gany<64>(act, 0)) return false;
+    if (act && i == 0) publish_d<NP>(g, 0, rbd0);
 #pragma unroll NP
-        for (int k = 0; k < NP; ++k) {
-            if (k < N) {
-                const double* buf = (k & 1) ? rbd1 : rbd0;
-                double* nbuf = (k & 1) ? rbd0 : rbd1;
-                if (do_emi) {
-                    const double p = buf[NP];
-                    gfail = gfail || !(p > kTauPivot && p <= 1.7976931348623157e308);
-                    if (i != k) {
-                        const double f = gi[k];
-                        gi[k] = 0.0;
+    for (int k = 0; k < NP; ++k) {
+        if (k < N) {
+            const double* buf = (k & 1) ? rbd1 : rbd0;
+            double* nbuf = (k & 1) ? rbd0 : rbd1;
+            if (act) {
+                const double p = buf[NP];
+                fail = fail || !(p > kTauPivot && p <= 1.7976931348623157e308);
+                if (i != k) {
+                    const double f = g[k];
+                    g[k] = 0.0;
 #pragma unroll
-                        for (int j = 0; j < NP; ++j) gi[j] = fma(-f, buf[j], gi[j]);
-                    }
-                    if (k + 1 < N && i == k + 1) publish_d<NP>(gi, (k + 1 < NP ? k + 1 : NP - 1), nbuf);
+                    for (int j = 0; j < NP; ++j) g[j] = fma(-f, buf[j], g[j]);
                 }
+                if (k + 1 < N && i == k + 1) publish_d<NP>(g, (k + 1 < NP ? k + 1 : NP - 1), nbuf);
             }
         }
     }
-    use_evd = use_evd || gfail;
+    return fail;
+}
 
-    // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
-    // of C is read again (an L2 hit) rather than kept live across step 1.
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        c[j] = make_float2(0.f, 0.f);
-        if (row_live && j < N) {
-            const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src) + j);
-            c[j] = make_float2(v.x, v.y);
-        }
-    }
-    float2* bme = &brow[0][threadIdx.x];  // element j at bme[j * kBlock]
-    float bnorm2 = 0.f;  // ||row i of B||^2
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        float2 v;
-        if (use_evd) v = make_float2(-c[j].x, -c[j].y);
-        else v = make_float2((float)gi[j] * c[j].x, (float)gi[j] * c[j].y);
-        bme[j * kBlock] = v;
-        bnorm2 += v.x * v.x + v.y * v.y;
-    }
-    float mu = use_evd ? evd_shift : 0.99f;
-
-    // ---- 3. shifted inverse iteration.  One factorisation site serves the
-    // first shift and its back-off schedule, the refined shifts, and restoring
-    // the accepted shift after every refined candidate was rejected.
-    float2 m[NP];
+// Eigenvector of the smallest eigenvalue of the Hermitian B (this lane's
+// row in LDS at bme[j * kBlock]) by shifted inverse iteration starting from
+// x (unit norm).  On return m holds (B - mu I)^{-1} for the last accepted
+// shift, x the unit eigenvector component of this lane.
+template <int NP>
+__device__ void eig_min(float2 (&m)[NP], const float2* bme, float bnorm2, float mu, bool solve,
+                        int N, int i, float2* rbc0, float2* rbc1, float2* xb, float2& x,
+                        bool& conv, int& it, int& retries) {
+    // One factorisation site serves the first shift and its back-off
+    // schedule, the refined shifts, and restoring the accepted shift after
+    // every refined candidate was rejected.
 #pragma unroll
     for (int j = 0; j < NP; ++j) m[j] = make_float2(0.f, 0.f);
-    const bool solve = !invalid;
     float mu_req = mu;    // shift of the pending factorisation
     bool need = solve;    // this group waits for a factorisation
     int stage = 0;        // 0..3: first-shift schedule, 4: refining, 5: restoring
     int cand = 0;         // refined candidate rho - kRefine[cand] * res
     float rho_t = 0.f, res_t = 0.f;
-    bool conv = !solve;
-    int it = 0, retries = 0;
+    conv = !solve;
+    it = 0;
+    retries = 0;
     float d2prev = 0.f;
     for (int guard = 0; guard < 2 * kMaxIter; ++guard) {
         if (gany<64>(need, 0)) {
@@ -401,6 +316,112 @@ void phase_link_kernel(LinkArgs a) {
             }
         }
     }
+
+}
+
+template <int NP>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
+void phase_link_kernel(LinkArgs a) {
+    constexpr int GPW = 64 / NP;  // groups (pixels) per wavefront
+    // per group: two GJ pivot-row buffers (NP + 2 doubles each, also used as
+    // NP + 2 float2) and the iterate buffer (NP float2)
+    constexpr int ROW_BYTES = (NP + 2) * 8;
+    constexpr int GROUP_BYTES = 2 * ROW_BYTES + NP * 8;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[(kBlock / 64) * GPW * GROUP_BYTES];
+    // row i of B for every lane, element-major so that the lanes of a
+    // wavefront read consecutive words: read back for refactorisations and
+    // Rayleigh quotients instead of occupying registers through the iteration
+    __shared__ __attribute__((aligned(16))) float2 brow[NP][kBlock];
+    const int lane = lane_id();
+    const int i = lane & (NP - 1);
+    const int grp = lane / NP;
+    const int wave = threadIdx.x >> 6;
+    unsigned char* gbase = lds + (wave * GPW + grp) * GROUP_BYTES;
+    double* rbd0 = reinterpret_cast<double*>(gbase);
+    double* rbd1 = reinterpret_cast<double*>(gbase + ROW_BYTES);
+    float2* rbc0 = reinterpret_cast<float2*>(gbase);
+    float2* rbc1 = reinterpret_cast<float2*>(gbase + ROW_BYTES);
+    float2* xb = reinterpret_cast<float2*>(gbase + 2 * ROW_BYTES);
+
+    const int N = a.N;
+    const int64_t pix = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * GPW + grp;
+    const bool active = pix < a.npix;
+    const bool row_live = active && i < N;
+
+    // ---- load row i of C
+    float2 c[NP];
+    const float2* src = a.coh + (active ? pix : 0) * (int64_t)N * N + (int64_t)i * N;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
+    const bool invalid = !active || gany<NP>(bad, grp);
+
+    // start from column ref of C: the single-reference interferogram phases
+    float2 x = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+        if (j == a.ref && row_live) x = c[j];
+    {
+        float nrm = gsum<NP>(x.x * x.x + x.y * x.y);
+        if (!(nrm > 0.f)) {
+            x = make_float2(i == a.ref ? 1.f : 0.f, 0.f);
+            nrm = 1.f;
+        }
+        const float s = 1.0f / sqrtf(nrm);
+        x.x *= s;
+        x.y *= s;
+    }
+    // EVD shift: minus a Gershgorin bound on lambda_max(C), so -C - mu I > 0
+    float evd_shift;
+    {
+        float rs = 0.f;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) rs += sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
+        evd_shift = -(1.0f + 1e-3f) * gmax<NP>(rs) - 1e-3f;
+    }
+
+    // ---- 1. FP64 inverse of G = |C|
+    bool use_evd = a.method == PL_LINK_EVD;
+    double gi[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        const double re = c[j].x, im = c[j].y;
+        gi[j] = (row_live && j < N) ? sqrt(fma(re, re, im * im)) : 0.0;
+    }
+    const bool do_emi = !use_evd && !invalid;
+    const bool gfail = invert_g<NP>(gi, N, i, do_emi, rbd0, rbd1);
+    use_evd = use_evd || gfail;
+
+    // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
+    // of C is read again (an L2 hit) rather than kept live across step 1.
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        c[j] = make_float2(0.f, 0.f);
+        if (row_live && j < N) {
+            const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src) + j);
+            c[j] = make_float2(v.x, v.y);
+        }
+    }
+    float2* bme = &brow[0][threadIdx.x];  // element j at bme[j * kBlock]
+    float bnorm2 = 0.f;  // ||row i of B||^2
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        float2 v;
+        if (use_evd) v = make_float2(-c[j].x, -c[j].y);
+        else v = make_float2((float)gi[j] * c[j].x, (float)gi[j] * c[j].y);
+        bme[j * kBlock] = v;
+        bnorm2 += v.x * v.x + v.y * v.y;
+    }
+    float mu = use_evd ? evd_shift : 0.99f;
+
+    // ---- 3. shifted inverse iteration
+    float2 m[NP];
+    bool conv;
+    int it, retries;
+    eig_min<NP>(m, bme, bnorm2, mu, !invalid, N, i, rbc0, rbc1, xb, x, conv, it, retries);
 
     // ---- 4. eigenvalue, reference and unit phasors
     const float2 bx = matvec_lds<NP>(bme, x, i, xb);
