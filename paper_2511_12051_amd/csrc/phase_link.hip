@@ -95,30 +95,30 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // FP64 counterpart of publish_c without a shift.
-template <int NP>
-__device__ __forceinline__ void publish_d(double (&g)[NP], int k, double* buf) {
+template <int NJ>
+__device__ __forceinline__ void publish_d(double (&g)[NJ], int k, double* buf) {
     const double p = g[k];
     const double inv = 1.0 / p;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) g[j] *= inv;
+    for (int j = 0; j < NJ; ++j) g[j] *= inv;
     g[k] = inv;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) buf[j] = g[j];
-    buf[NP] = p;
+    for (int j = 0; j < NJ; ++j) buf[j] = g[j];
+    buf[NJ] = p;
 }
 
 // Scales this lane's row k by 1/p, p = m[k] - mu, stores 1/p at k (in-place
 // Gauss-Jordan form) and publishes the row and p for the group.
-template <int NP>
-__device__ __forceinline__ void publish_c(float2 (&m)[NP], int k, float mu, float2* buf) {
+template <int NJ>
+__device__ __forceinline__ void publish_c(float2 (&m)[NJ], int k, float mu, float2* buf) {
     const float p = m[k].x - mu;
     const float inv = 1.0f / p;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) m[j] = make_float2(m[j].x * inv, m[j].y * inv);
+    for (int j = 0; j < NJ; ++j) m[j] = make_float2(m[j].x * inv, m[j].y * inv);
     m[k] = make_float2(inv, 0.f);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) buf[j] = m[j];
-    buf[NP] = make_float2(p, 0.f);
+    for (int j = 0; j < NJ; ++j) buf[j] = m[j];
+    buf[NJ] = make_float2(p, 0.f);
 }
 
 // In-place complex Gauss-Jordan inversion of the Hermitian matrix (m - mu I),
@@ -130,41 +130,41 @@ __device__ __forceinline__ void publish_c(float2 (&m)[NP], int k, float mu, floa
 // its step-k update (double-buffered), so each step costs one LDS round trip.
 // All lanes of a group belong to one wavefront and its LDS operations execute
 // in program order, so no barrier is needed between publishing and reading.
-template <int NP>
-__device__ bool invert_c(float2 (&m)[NP], float mu, int N, int i, bool act, float2* rb0, float2* rb1) {
+template <int NJ>
+__device__ bool invert_c(float2 (&m)[NJ], float mu, int N, int i, bool act, float2* rb0, float2* rb1) {
     bool pd = true;
-    if (act && i == 0) publish_c<NP>(m, 0, mu, rb0);
-#pragma unroll NP
-    for (int k = 0; k < NP; ++k) {
+    if (act && i == 0) publish_c<NJ>(m, 0, mu, rb0);
+#pragma unroll NJ
+    for (int k = 0; k < NJ; ++k) {
         if (k < N) {
             const float2* buf = (k & 1) ? rb1 : rb0;
             float2* nbuf = (k & 1) ? rb0 : rb1;
             if (act) {
-                const float p = buf[NP].x;
+                const float p = buf[NJ].x;
                 pd = pd && (p > 0.f) && (p <= 3.4e38f);
                 if (i != k) {
                     const float2 f = m[k];
                     m[k] = make_float2(0.f, 0.f);
 #pragma unroll
-                    for (int j = 0; j < NP; ++j) {
+                    for (int j = 0; j < NJ; ++j) {
                         const float2 r = buf[j];
                         m[j].x = fmaf(-f.x, r.x, fmaf(f.y, r.y, m[j].x));
                         m[j].y = fmaf(-f.x, r.y, fmaf(-f.y, r.x, m[j].y));
                     }
                 }
-                if (k + 1 < N && i == k + 1) publish_c<NP>(m, (k + 1 < NP ? k + 1 : NP - 1), mu, nbuf);
+                if (k + 1 < N && i == k + 1) publish_c<NJ>(m, (k + 1 < NJ ? k + 1 : NJ - 1), mu, nbuf);
             }
         }
     }
     return pd;
 }
 
-template <int NP>
-__device__ __forceinline__ float2 matvec(const float2 (&m)[NP], float2 x, int i, float2* xb) {
+template <int NJ>
+__device__ __forceinline__ float2 matvec(const float2 (&m)[NJ], float2 x, int i, float2* xb) {
     xb[i] = x;  // read back below by the other lanes (in-order LDS)
     float2 y = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const float2 v = xb[j];
         y.x = fmaf(m[j].x, v.x, fmaf(-m[j].y, v.y, y.x));
         y.y = fmaf(m[j].x, v.y, fmaf(m[j].y, v.x, y.y));
@@ -173,12 +173,12 @@ __device__ __forceinline__ float2 matvec(const float2 (&m)[NP], float2 x, int i,
 }
 
 // y_i = sum_j B_ij x_j with this lane's row of B in LDS (stride kBlock).
-template <int NP>
+template <int NJ>
 __device__ __forceinline__ float2 matvec_lds(const float2* brow, float2 x, int i, float2* xb) {
     xb[i] = x;
     float2 y = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const float2 v = xb[j], m = brow[j * kBlock];
         y.x = fmaf(m.x, v.x, fmaf(-m.y, v.y, y.x));
         y.y = fmaf(m.x, v.y, fmaf(m.y, v.x, y.y));
@@ -189,26 +189,26 @@ __device__ __forceinline__ float2 matvec_lds(const float2* brow, float2 x, int i
 // In-place FP64 Gauss-Jordan inversion of G (row i = this lane's g[]) for
 // lanes with act; returns (per group) whether some pivot was <= 1e-6 or not
 // finite, i.e. the inversion failed.  Same publishing scheme as invert_c.
-template <int NP>
-__device__ bool invert_g(double (&g)[NP], int N, int i, bool act, double* rbd0, double* rbd1) {
+template <int NJ>
+__device__ bool invert_g(double (&g)[NJ], int N, int i, bool act, double* rbd0, double* rbd1) {
     bool fail = false;
     if (!gany<64>(act, 0)) return false;
-    if (act && i == 0) publish_d<NP>(g, 0, rbd0);
-#pragma unroll NP
-    for (int k = 0; k < NP; ++k) {
+    if (act && i == 0) publish_d<NJ>(g, 0, rbd0);
+#pragma unroll NJ
+    for (int k = 0; k < NJ; ++k) {
         if (k < N) {
             const double* buf = (k & 1) ? rbd1 : rbd0;
             double* nbuf = (k & 1) ? rbd0 : rbd1;
             if (act) {
-                const double p = buf[NP];
+                const double p = buf[NJ];
                 fail = fail || !(p > kTauPivot && p <= 1.7976931348623157e308);
                 if (i != k) {
                     const double f = g[k];
                     g[k] = 0.0;
 #pragma unroll
-                    for (int j = 0; j < NP; ++j) g[j] = fma(-f, buf[j], g[j]);
+                    for (int j = 0; j < NJ; ++j) g[j] = fma(-f, buf[j], g[j]);
                 }
-                if (k + 1 < N && i == k + 1) publish_d<NP>(g, (k + 1 < NP ? k + 1 : NP - 1), nbuf);
+                if (k + 1 < N && i == k + 1) publish_d<NJ>(g, (k + 1 < NJ ? k + 1 : NJ - 1), nbuf);
             }
         }
     }
@@ -217,17 +217,24 @@ __device__ bool invert_g(double (&g)[NP], int N, int i, bool act, double* rbd0, 
 
 // Eigenvector of the smallest eigenvalue of the Hermitian B (this lane's
 // row in LDS at bme[j * kBlock]) by shifted inverse iteration starting from
-// x (unit norm).  On return m holds (B - mu I)^{-1} for the last accepted
-// shift, x the unit eigenvector component of this lane.
-template <int NP>
-__device__ void eig_min(float2 (&m)[NP], const float2* bme, float bnorm2, float mu, bool solve,
-                        int N, int i, float2* rbc0, float2* rbc1, float2* xb, float2& x,
+// x (unit norm, component ref_lane real and positive).  On return m holds
+// (B - mu I)^{-1} for the last accepted shift, x the unit eigenvector
+// component of this lane.
+//
+// Every iterate is rotated so that its component at ref_lane (the lane of the
+// reference image in this group) is real and positive.  In FP32 the computed
+// inverse is not exactly Hermitian, so its dominant eigenvalue carries a small
+// phase; without the rotation each step turns the converged vector by that
+// phase and the step length never falls below the tolerance.
+template <int NP, int NJ>
+__device__ void eig_min(float2 (&m)[NJ], const float2* bme, float bnorm2, float mu, bool solve,
+                        int N, int i, int ref_lane, float2* rbc0, float2* rbc1, float2* xb, float2& x,
                         bool& conv, int& it, int& retries) {
     // One factorisation site serves the first shift and its back-off
     // schedule, the refined shifts, and restoring the accepted shift after
     // every refined candidate was rejected.
 #pragma unroll
-    for (int j = 0; j < NP; ++j) m[j] = make_float2(0.f, 0.f);
+    for (int j = 0; j < NJ; ++j) m[j] = make_float2(0.f, 0.f);
     float mu_req = mu;    // shift of the pending factorisation
     bool need = solve;    // this group waits for a factorisation
     int stage = 0;        // 0..3: first-shift schedule, 4: refining, 5: restoring
@@ -240,8 +247,8 @@ __device__ void eig_min(float2 (&m)[NP], const float2* bme, float bnorm2, float 
     for (int guard = 0; guard < 2 * kMaxIter; ++guard) {
         if (gany<64>(need, 0)) {
 #pragma unroll
-            for (int j = 0; j < NP; ++j) if (need) m[j] = bme[j * kBlock];
-            const bool ok = invert_c<NP>(m, mu_req, N, i, need, rbc0, rbc1);
+            for (int j = 0; j < NJ; ++j) if (need) m[j] = bme[j * kBlock];
+            const bool ok = invert_c<NJ>(m, mu_req, N, i, need, rbc0, rbc1);
             if (need) {
                 if (ok) {
                     if (stage == 4) d2prev = 0.f;  // the contraction rate changes
@@ -277,11 +284,15 @@ __device__ void eig_min(float2 (&m)[NP], const float2* bme, float bnorm2, float 
             continue;
         }
         if (!gany<64>(!conv, 0) || it >= kMaxIter) break;
-        float2 y = matvec<NP>(m, x, i, xb);
+        float2 y = matvec<NJ>(m, x, i, xb);
         const float n2 = gsum<NP>(y.x * y.x + y.y * y.y);
-        const float sc = 1.0f / sqrtf(n2);
-        y.x *= sc;
-        y.y *= sc;
+        const float2 yr = make_float2(__shfl(y.x, ref_lane, 64), __shfl(y.y, ref_lane, 64));
+        const float r2 = yr.x * yr.x + yr.y * yr.y;
+        // scale by conj(y_ref) / (|y_ref| ||y||); plain 1/||y|| if y_ref vanishes
+        const bool gauge = r2 > 1e-30f * n2;
+        const float sc = gauge ? 1.0f / sqrtf(n2 * r2) : 1.0f / sqrtf(n2);
+        const float2 u = gauge ? make_float2(yr.x * sc, -yr.y * sc) : make_float2(sc, 0.f);
+        y = cmul(y, u);
         const float dx = y.x - x.x, dy = y.y - x.y;
         const float d2 = gsum<NP>(dx * dx + dy * dy);
         const bool finite = n2 > 0.f && n2 <= 3.4e38f;
@@ -301,7 +312,7 @@ __device__ void eig_min(float2 (&m)[NP], const float2* bme, float bnorm2, float 
             // rejects it.
             const bool slow = !conv && q2 > kRefineRate * kRefineRate;
             if (gany<64>(slow, 0)) {
-                const float2 bx = matvec_lds<NP>(bme, x, i, xb);
+                const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
                 const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
                 const float rx = bx.x - rho * x.x, ry = bx.y - rho * x.y;
                 const float res = sqrtf(gsum<NP>(rx * rx + ry * ry));
@@ -319,19 +330,21 @@ __device__ void eig_min(float2 (&m)[NP], const float2* bme, float bnorm2, float 
 
 }
 
-template <int NP>
+template <int NP, int NJ>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
 void phase_link_kernel(LinkArgs a) {
     constexpr int GPW = 64 / NP;  // groups (pixels) per wavefront
-    // per group: two GJ pivot-row buffers (NP + 2 doubles each, also used as
-    // NP + 2 float2) and the iterate buffer (NP float2)
-    constexpr int ROW_BYTES = (NP + 2) * 8;
+    // NJ >= N columns are stored and updated per row (N rounded up to a
+    // multiple of 4); NP >= N lanes hold the rows.
+    // per group: two GJ pivot-row buffers (NJ + 2 doubles each, also used as
+    // NJ + 2 float2) and the iterate buffer (NP float2)
+    constexpr int ROW_BYTES = (NJ + 2) * 8;
     constexpr int GROUP_BYTES = 2 * ROW_BYTES + NP * 8;
     __shared__ __attribute__((aligned(16))) unsigned char lds[(kBlock / 64) * GPW * GROUP_BYTES];
     // row i of B for every lane, element-major so that the lanes of a
     // wavefront read consecutive words: read back for refactorisations and
     // Rayleigh quotients instead of occupying registers through the iteration
-    __shared__ __attribute__((aligned(16))) float2 brow[NP][kBlock];
+    __shared__ __attribute__((aligned(16))) float2 brow[NJ][kBlock];
     const int lane = lane_id();
     const int i = lane & (NP - 1);
     const int grp = lane / NP;
@@ -349,19 +362,19 @@ void phase_link_kernel(LinkArgs a) {
     const bool row_live = active && i < N;
 
     // ---- load row i of C
-    float2 c[NP];
+    float2 c[NJ];
     const float2* src = a.coh + (active ? pix : 0) * (int64_t)N * N + (int64_t)i * N;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
+    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
     bool bad = false;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
+    for (int j = 0; j < NJ; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
     const bool invalid = !active || gany<NP>(bad, grp);
 
     // start from column ref of C: the single-reference interferogram phases
     float2 x = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int j = 0; j < NP; ++j)
+    for (int j = 0; j < NJ; ++j)
         if (j == a.ref && row_live) x = c[j];
     {
         float nrm = gsum<NP>(x.x * x.x + x.y * x.y);
@@ -378,27 +391,27 @@ void phase_link_kernel(LinkArgs a) {
     {
         float rs = 0.f;
 #pragma unroll
-        for (int j = 0; j < NP; ++j) rs += sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
+        for (int j = 0; j < NJ; ++j) rs += sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
         evd_shift = -(1.0f + 1e-3f) * gmax<NP>(rs) - 1e-3f;
     }
 
     // ---- 1. FP64 inverse of G = |C|
     bool use_evd = a.method == PL_LINK_EVD;
-    double gi[NP];
+    double gi[NJ];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const double re = c[j].x, im = c[j].y;
         gi[j] = (row_live && j < N) ? sqrt(fma(re, re, im * im)) : 0.0;
     }
     const bool do_emi = !use_evd && !invalid;
-    const bool gfail = invert_g<NP>(gi, N, i, do_emi, rbd0, rbd1);
+    const bool gfail = invert_g<NJ>(gi, N, i, do_emi, rbd0, rbd1);
     use_evd = use_evd || gfail;
 
     // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
     // of C is read again (an L2 hit) rather than kept live across step 1.
     typedef float f32x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         c[j] = make_float2(0.f, 0.f);
         if (row_live && j < N) {
             const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src) + j);
@@ -408,7 +421,7 @@ void phase_link_kernel(LinkArgs a) {
     float2* bme = &brow[0][threadIdx.x];  // element j at bme[j * kBlock]
     float bnorm2 = 0.f;  // ||row i of B||^2
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         float2 v;
         if (use_evd) v = make_float2(-c[j].x, -c[j].y);
         else v = make_float2((float)gi[j] * c[j].x, (float)gi[j] * c[j].y);
@@ -418,13 +431,13 @@ void phase_link_kernel(LinkArgs a) {
     float mu = use_evd ? evd_shift : 0.99f;
 
     // ---- 3. shifted inverse iteration
-    float2 m[NP];
+    float2 m[NJ];
     bool conv;
     int it, retries;
-    eig_min<NP>(m, bme, bnorm2, mu, !invalid, N, i, rbc0, rbc1, xb, x, conv, it, retries);
+    eig_min<NP, NJ>(m, bme, bnorm2, mu, !invalid, N, i, grp * NP + a.ref, rbc0, rbc1, xb, x, conv, it, retries);
 
     // ---- 4. eigenvalue, reference and unit phasors
-    const float2 bx = matvec_lds<NP>(bme, x, i, xb);
+    const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
     const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
     const float2 xr = make_float2(__shfl(x.x, grp * NP + a.ref, 64), __shfl(x.y, grp * NP + a.ref, 64));
     float2 z = make_float2(x.x * xr.x + x.y * xr.y, x.y * xr.x - x.x * xr.y);  // x conj(x_ref)
@@ -464,8 +477,15 @@ pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int
     const int64_t per_block = (kBlock / 64) * (64 / np);
     const int64_t blocks = (npix + per_block - 1) / per_block;
     if (blocks > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link: too many pixels");
-    if (np == 16) hipLaunchKernelGGL(phase_link_kernel<16>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(phase_link_kernel<32>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    switch ((N + 3) / 4) {  // columns per row: N rounded up to a multiple of 4
+        case 1: case 2: case 3: hipLaunchKernelGGL((phase_link_kernel<16, 12>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((phase_link_kernel<16, 16>), grid, block, 0, s, a); break;
+        case 5: hipLaunchKernelGGL((phase_link_kernel<32, 20>), grid, block, 0, s, a); break;
+        case 6: hipLaunchKernelGGL((phase_link_kernel<32, 24>), grid, block, 0, s, a); break;
+        case 7: hipLaunchKernelGGL((phase_link_kernel<32, 28>), grid, block, 0, s, a); break;
+        default: hipLaunchKernelGGL((phase_link_kernel<32, 32>), grid, block, 0, s, a); break;
+    }
     return launch_ok("phase linking kernel");
 }
 
