@@ -152,13 +152,40 @@ pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64
  * the eigenvector of the largest eigenvalue of C.  The result is referenced to
  * image ref_idx (Sec. 2.1: multiplied by conj(zeta_r)) and returned as unit
  * phasors.  coh: [npix][N][N]; phasors: [N][npix] (phasors[ref_idx] = 1);
- * lambda: [npix] or NULL (eigenvalue of the vector: lambda_min of
+ * phase: [N][npix] or NULL, the same result as angles in (-pi, pi] (0 at
+ * ref_idx and at invalid pixels); lambda: [npix] or NULL (eigenvalue of the vector: lambda_min of
  * |C|^{-1} o C for EMI, lambda_max of C for EVD); flags: [npix] or NULL
  * (PL_FLAG_*); invalid pixels (non-finite C) get phasors 1.
  * counters: optional.  npix = 0 is a no-op (pointers may then be NULL). */
 pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
-                        pl_link_method method, pl_c64* phasors, float* lambda, uint8_t* flags,
-                        uint64_t* counters, pl_stream stream);
+                        pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
+                        uint8_t* flags, uint64_t* counters, pl_stream stream);
+
+/* ------------------------------------------- adjoint of coherence + link
+ * Vector-Jacobian product of the linked phases phi_i = arg(v_i conj(v_ref))
+ * with respect to the stack, through the sample coherence and the EMI / EVD
+ * eigenvector (Sec. 2.1 eq. sample-coherence, Sec. 3.2
+ * eq. emi-eigenvalue-problem), with the SHP mask and each pixel's EMI/EVD
+ * choice held fixed (both are piecewise constant in the stack).  Per pixel,
+ * with A = sum z z^H over the SHPs, C = D^-1/2 A D^-1/2, G = |C|,
+ * H = G^-1 o C (EMI) or -C (EVD) and (v, lambda) its smallest eigenpair:
+ *   dphi_i = Im(dv_i / v_i) - Im(dv_ref / v_ref),
+ *   dv = -(H - lambda I)^+ dH v,  dH = -(G^-1 dG G^-1) o C + G^-1 o dC,
+ *   dG = Re(conj(C) o dC) / |C|,  dA = sum (dz z^H + z dz^H).
+ * The coherence and the eigenpair are recomputed here (prec must be the one
+ * of the forward pass so that C is the same).
+ * stack: [N][R][C]; mask: [oR][oC][nwords]; flags: [oR*oC] from
+ * pl_phase_link (PL_FLAG_INVALID pixels contribute nothing); grad_phase:
+ * [N][oR*oC] float, dL/dphi; grad_stack: [N][R][C] written (not accumulated)
+ * with dL/dRe z + j dL/dIm z.  workspace: device memory of at least
+ * pl_phase_link_vjp_workspace() bytes, owned by the caller, contents
+ * irrelevant on entry.  Pixels whose value z is not finite get non-finite
+ * gradients.  Errors: PL_ERR_WORKSPACE when ws_bytes is too small. */
+pl_status pl_phase_link_vjp_workspace(int32_t N, int64_t R, int64_t C, pl_window w, size_t* bytes);
+pl_status pl_phase_link_vjp(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                            const uint32_t* mask, const uint8_t* flags, int32_t ref_idx,
+                            pl_precision prec, const float* grad_phase, pl_c64* grad_stack,
+                            void* workspace, size_t ws_bytes, pl_stream stream);
 
 /* ------------------------------------------------------ compressed SLC
  * Compressed SLC of a mini-stack (Sec. 2.2): kappa = zeta^H z over the real

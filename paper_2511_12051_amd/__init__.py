@@ -19,7 +19,8 @@ import torch
 __all__ = [
     "PlinkError", "load", "library_path", "output_grid", "mask_words", "amplitude_stats",
     "merge_amplitude_stats", "shp_select", "estimate_coherence", "phase_link",
-    "compress_ministack", "Sequential", "new_counters", "COUNTERS", "FLAG_EMI", "FLAG_EVD",
+    "compress_ministack", "Sequential", "new_counters", "phase_link_vjp", "phase_link_vjp_workspace",
+    "PhaseLink", "COUNTERS", "FLAG_EMI", "FLAG_EVD",
     "FLAG_INVALID", "MAX_N",
 ]
 
@@ -66,7 +67,10 @@ _SIGNATURES = {
     "pl_merge_amplitude_stats": (ctypes.c_int, [_P, _P, ctypes.POINTER(_D), _I32, _I64, _I64, _P, _P, _P]),
     "pl_shp_select": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _Window, _D, _P, _P, _P, _P]),
     "pl_estimate_coherence": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, ctypes.c_int, _P, _P]),
-    "pl_phase_link": (ctypes.c_int, [_P, _I32, _I64, _I32, ctypes.c_int, _P, _P, _P, _P, _P]),
+    "pl_phase_link": (ctypes.c_int, [_P, _I32, _I64, _I32, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "pl_phase_link_vjp_workspace": (ctypes.c_int, [_I32, _I64, _I64, _Window, ctypes.POINTER(ctypes.c_size_t)]),
+    "pl_phase_link_vjp": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, _P, _I32, ctypes.c_int, _P, _P,
+                                         _P, ctypes.c_size_t, _P]),
     "pl_compress_ministack": (ctypes.c_int, [_P, _I32, _I32, _I64, _I64, _Window, _P, _P, _P]),
     "pl_seq_create": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(_P)]),
     "pl_seq_destroy": (ctypes.c_int, [_P]),
@@ -201,18 +205,81 @@ def estimate_coherence(stack: torch.Tensor, mask: torch.Tensor, window, precisio
     return coh
 
 
-def phase_link(coh: torch.Tensor, ref: int = 0, method="emi", counters=None):
-    """EMI (EVD fallback) linked phasors: [P,N,N] -> (phasors [N,P], lambda [P], flags uint8 [P])."""
+def phase_link(coh: torch.Tensor, ref: int = 0, method="emi", counters=None, want_phase=False):
+    """EMI (EVD fallback) linked phasors: [P,N,N] -> (phasors [N,P], lambda [P], flags uint8 [P]),
+    plus the phases [N,P] (float32, radians) as a fourth element when want_phase."""
     _need(coh, torch.complex64, 3, "phase_link")
     P, N, N2 = coh.shape
     if N != N2:
         raise PlinkError("phase_link: matrices must be square")
     ph = torch.empty((N, P), dtype=torch.complex64, device=coh.device)
+    phase = torch.empty((N, P), dtype=torch.float32, device=coh.device) if want_phase else None
     lam = torch.empty((P,), dtype=torch.float32, device=coh.device)
     flags = torch.empty((P,), dtype=torch.uint8, device=coh.device)
-    _check(load().pl_phase_link(_ptr(coh), N, P, int(ref), _METHOD[method], _ptr(ph), _ptr(lam),
-                                _ptr(flags), _ptr(counters), _stream(coh)), "phase_link")
-    return ph, lam, flags
+    _check(load().pl_phase_link(_ptr(coh), N, P, int(ref), _METHOD[method], _ptr(ph), _ptr(phase),
+                                _ptr(lam), _ptr(flags), _ptr(counters), _stream(coh)), "phase_link")
+    return (ph, lam, flags, phase) if want_phase else (ph, lam, flags)
+
+
+def phase_link_vjp_workspace(N: int, R: int, C: int, window) -> int:
+    """Bytes of device workspace that phase_link_vjp needs."""
+    n = ctypes.c_size_t()
+    _check(load().pl_phase_link_vjp_workspace(int(N), int(R), int(C), _win(window), ctypes.byref(n)),
+           "phase_link_vjp_workspace")
+    return n.value
+
+
+def phase_link_vjp(stack: torch.Tensor, mask: torch.Tensor, flags: torch.Tensor, window, ref: int,
+                   grad_phase: torch.Tensor, precision="fp32", workspace: torch.Tensor | None = None):
+    """dL/dz (as dL/dRe + j dL/dIm, complex64 [N,R,C]) of the linked phases given
+    dL/dphi (float32 [N, oR*oC] or [N,oR,oC]); mask and EMI/EVD flags held fixed."""
+    _need(stack, torch.complex64, 3, "phase_link_vjp")
+    _need(mask, torch.int32, 3, "phase_link_vjp mask")
+    N, R, C = stack.shape
+    oR, oC = output_grid(R, C, window)
+    if tuple(mask.shape) != (oR, oC, mask_words(window)):
+        raise PlinkError("phase_link_vjp: mask shape does not match the window")
+    if flags.dtype != torch.uint8 or flags.numel() != oR * oC or not flags.is_contiguous():
+        raise PlinkError("phase_link_vjp: flags must be contiguous uint8 [oR*oC]")
+    if (grad_phase.dtype != torch.float32 or grad_phase.numel() != N * oR * oC
+            or not grad_phase.is_contiguous() or grad_phase.device != stack.device):
+        raise PlinkError("phase_link_vjp: grad_phase must be contiguous float32 [N, oR*oC] on the stack's GPU")
+    need = phase_link_vjp_workspace(N, R, C, window)
+    if workspace is None:
+        workspace = torch.empty((need,), dtype=torch.uint8, device=stack.device)
+    grad = torch.empty_like(stack)
+    _check(load().pl_phase_link_vjp(_ptr(stack), N, R, C, _win(window), _ptr(mask), _ptr(flags), int(ref),
+                                    _PREC[precision], _ptr(grad_phase), _ptr(grad), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(), _stream(stack)),
+           "phase_link_vjp")
+    return grad
+
+
+class PhaseLink(torch.autograd.Function):
+    """Linked phases [N, oR, oC] of a stack [N, R, C] (complex64) for a fixed SHP
+    mask, differentiable with respect to the stack.  The forward runs the
+    coherence and linking kernels; the backward recomputes the coherence and
+    the eigen-solve inside the adjoint kernels (only the stack, the mask and
+    the per-pixel EMI/EVD flags are kept)."""
+
+    @staticmethod
+    def forward(ctx, stack, mask, window, ref=0, precision="fp32", method="emi"):
+        N, R, C = stack.shape
+        oR, oC = output_grid(R, C, window)
+        coh = estimate_coherence(stack, mask, window, precision)
+        _, _, flags, phase = phase_link(coh, ref, method, want_phase=True)
+        del coh
+        ctx.save_for_backward(stack, mask, flags)
+        ctx.window, ctx.ref, ctx.precision = tuple(window), int(ref), precision
+        ctx.mark_non_differentiable(flags)
+        return phase.view(N, oR, oC), flags
+
+    @staticmethod
+    def backward(ctx, grad_phase, grad_flags=None):
+        stack, mask, flags = ctx.saved_tensors
+        g = grad_phase.to(torch.float32).contiguous()
+        grad = phase_link_vjp(stack, mask, flags, ctx.window, ctx.ref, g, ctx.precision)
+        return grad, None, None, None, None, None
 
 
 def compress_ministack(stack: torch.Tensor, first_real: int, window, phasors: torch.Tensor):

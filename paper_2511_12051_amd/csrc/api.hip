@@ -157,12 +157,12 @@ pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64
     PL_CHECK(prec == PL_PREC_FP32 || prec == PL_PREC_SPLIT_BF16, PL_ERR_INVALID_ARG,
              "pl_estimate_coherence: unknown precision %d", (int)prec);
     PlaneTable t = contiguous_planes(stack, N, R * C);
-    return launch_coherence(t, N, g, mask, (int)prec, reinterpret_cast<float2*>(coh), S(stream));
+    return launch_coherence(t, N, g, mask, (int)prec, reinterpret_cast<float2*>(coh), nullptr, S(stream));
 }
 
 pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
-                        pl_link_method method, pl_c64* phasors, float* lambda, uint8_t* flags,
-                        uint64_t* counters, pl_stream stream) {
+                        pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
+                        uint8_t* flags, uint64_t* counters, pl_stream stream) {
     PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_phase_link: N=%d outside 1..%d", N, kMaxN);
     PL_CHECK(npix >= 0, PL_ERR_SHAPE, "pl_phase_link: negative pixel count");
     PL_CHECK(npix == 0 || (coh && phasors), PL_ERR_INVALID_ARG, "pl_phase_link: NULL pointer");
@@ -172,8 +172,61 @@ pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_
              "pl_phase_link: unknown method %d", (int)method);
     if (npix == 0) return PL_OK;
     return launch_phase_link(reinterpret_cast<const float2*>(coh), N, npix, ref_idx, (int)method,
-                             reinterpret_cast<float2*>(phasors), lambda, flags,
+                             reinterpret_cast<float2*>(phasors), phase, lambda, flags,
                              reinterpret_cast<unsigned long long*>(counters), S(stream));
+}
+
+// workspace of the adjoint: C [P][N][N] c64 | diag(A) [P][N] f32 |
+// S [N(N+1)/2][P] c64, each 256-byte aligned
+static size_t vjp_layout(int N, int64_t P, size_t* off_diag, size_t* off_s) {
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t coh = up((size_t)P * N * N * 8);
+    const size_t diag = up((size_t)P * N * 4);
+    const size_t sb = up((size_t)P * (N * (N + 1) / 2) * 8);
+    if (off_diag) *off_diag = coh;
+    if (off_s) *off_s = coh + diag;
+    return coh + diag + sb;
+}
+
+pl_status pl_phase_link_vjp_workspace(int32_t N, int64_t R, int64_t C, pl_window w, size_t* bytes) {
+    Geometry g;
+    PL_CHECK(bytes, PL_ERR_INVALID_ARG, "pl_phase_link_vjp_workspace: NULL output");
+    PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_phase_link_vjp_workspace: N=%d outside 1..%d", N, kMaxN);
+    PL_CHECK(make_geometry(R, C, w, &g), PL_ERR_SHAPE, "pl_phase_link_vjp_workspace: bad image size or window");
+    PL_CHECK(g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE, "pl_phase_link_vjp_workspace: image smaller than one stride");
+    *bytes = vjp_layout(N, g.oR * g.oC, nullptr, nullptr);
+    return PL_OK;
+}
+
+pl_status pl_phase_link_vjp(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                            const uint32_t* mask, const uint8_t* flags, int32_t ref_idx,
+                            pl_precision prec, const float* grad_phase, pl_c64* grad_stack,
+                            void* workspace, size_t ws_bytes, pl_stream stream) {
+    Geometry g;
+    PL_CHECK(stack && mask && flags && grad_phase && grad_stack && workspace, PL_ERR_INVALID_ARG,
+             "pl_phase_link_vjp: NULL pointer");
+    PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_phase_link_vjp: N=%d outside 1..%d", N, kMaxN);
+    PL_CHECK(make_geometry(R, C, w, &g), PL_ERR_SHAPE, "pl_phase_link_vjp: bad image size or window");
+    PL_CHECK(g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE, "pl_phase_link_vjp: image smaller than one stride");
+    PL_CHECK(ref_idx >= 0 && ref_idx < N, PL_ERR_INVALID_ARG, "pl_phase_link_vjp: ref_idx %d outside 0..%d",
+             ref_idx, N - 1);
+    PL_CHECK(prec == PL_PREC_FP32 || prec == PL_PREC_SPLIT_BF16, PL_ERR_INVALID_ARG,
+             "pl_phase_link_vjp: unknown precision %d", (int)prec);
+    const int64_t P = g.oR * g.oC;
+    size_t off_diag = 0, off_s = 0;
+    const size_t need = vjp_layout(N, P, &off_diag, &off_s);
+    PL_CHECK(ws_bytes >= need, PL_ERR_WORKSPACE, "pl_phase_link_vjp: workspace of %zu bytes, %zu needed",
+             ws_bytes, need);
+    unsigned char* ws = static_cast<unsigned char*>(workspace);
+    float2* coh = reinterpret_cast<float2*>(ws);
+    float* diag = reinterpret_cast<float*>(ws + off_diag);
+    float2* Sm = reinterpret_cast<float2*>(ws + off_s);
+    PlaneTable t = contiguous_planes(stack, N, R * C);
+    pl_status r = launch_coherence(t, N, g, mask, (int)prec, coh, diag, S(stream));
+    if (r != PL_OK) return r;
+    r = launch_link_vjp(coh, diag, flags, grad_phase, N, P, ref_idx, Sm, S(stream));
+    if (r != PL_OK) return r;
+    return launch_vjp_gather(t, N, g, mask, Sm, reinterpret_cast<float2*>(grad_stack), S(stream));
 }
 
 pl_status pl_compress_ministack(const pl_c64* stack, int32_t N, int32_t first_real, int64_t R,

@@ -53,6 +53,7 @@ struct CohArgs {
     Geometry g;
     const uint32_t* mask;
     float2* coh;
+    float* diag;      // optional [P][N] diagonal of A (SHP-summed |z|^2), or null
     int TXo;          // output columns per strip
     int rows_per_wg;  // output rows per workgroup
     int tile_w;       // staged input columns (even)
@@ -327,6 +328,7 @@ __device__ void store_pixel(const CohArgs& a, float* S, const typename Acc<NT>::
     const bool bad = (j < N) && !(dj > 0.f && dj <= 3.4e38f);
     const bool invalid = __ballot(bad) != 0;
     const float isj = 1.0f / sqrtf(dj);
+    if (a.diag && lane < NT && j < N) a.diag[pix * N + j] = dj;
     float2* out = a.coh + pix * (int64_t)N * N;
 #pragma unroll
     for (int v = 0; v < Acc<NT>::R; ++v) {
@@ -552,8 +554,9 @@ pl_status launch_variant(const CohArgs& a0, hipStream_t s) {
 }  // namespace
 
 pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
-                           int prec, float2* coh, hipStream_t s) {
+                           int prec, float2* coh, float* diag, hipStream_t s) {
     CohArgs a{};
+    a.diag = diag;
     a.t = t;
     a.N = N;
     a.g = g;

@@ -46,11 +46,20 @@ pl_status launch_merge_stats(const double* const* means, const double* const* va
 pl_status launch_shp_select(const double* mean, const double* var, const Geometry& g,
                             double n_eff, double alpha, uint32_t* mask, uint16_t* count,
                             unsigned long long* counters, hipStream_t s);
+// diag (optional, [P][N]) receives the diagonal of the unnormalised A
 pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
-                           int prec, float2* coh, hipStream_t s);
+                           int prec, float2* coh, float* diag, hipStream_t s);
 pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int method,
-                            float2* phasors, float* lambda, uint8_t* flags,
+                            float2* phasors, float* phase, float* lambda, uint8_t* flags,
                             unsigned long long* counters, hipStream_t s);
+// adjoint of coherence + linking: per-pixel S = Abar + Abar^H (upper
+// triangle, entry-major [N(N+1)/2][P]) from the recomputed coherence, then
+// grad z_q = sum over the windows holding q as an SHP of S_p z_q
+pl_status launch_link_vjp(const float2* coh, const float* diag, const uint8_t* flags,
+                          const float* grad_phase, int N, int64_t npix, int ref, float2* S,
+                          hipStream_t s);
+pl_status launch_vjp_gather(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
+                            const float2* S, float2* grad, hipStream_t s);
 pl_status launch_compress(const PlaneTable& t, int N, int first_real, const Geometry& g,
                           const float2* phasors, float2* kappa, hipStream_t s);
 

@@ -156,10 +156,10 @@ pl_status pl_seq_push(pl_seq* s, const pl_c64* new_slcs, pl_c64* phasors_out, pl
     PlaneTable t{};
     for (int j = 0; j < K; ++j) t.p[j] = s->kappa + ((k - K + j) % Kmax) * plane;
     for (int j = 0; j < M; ++j) t.p[K + j] = znew + j * plane;
-    r = launch_coherence(t, N, s->g, s->mask, p.precision, s->coh, st);
+    r = launch_coherence(t, N, s->g, s->mask, p.precision, s->coh, nullptr, st);
     if (r != PL_OK) return r;
     const int ref = K > 0 ? K - 1 : 0;  // the most recent compressed SLC
-    r = launch_phase_link(s->coh, N, s->opix, ref, p.method, s->phasors, nullptr, s->flags, cnt, st);
+    r = launch_phase_link(s->coh, N, s->opix, ref, p.method, s->phasors, nullptr, nullptr, s->flags, cnt, st);
     if (r != PL_OK) return r;
     // new compressed SLC over the real images; it replaces the oldest ring
     // entry, which the kernels above have already consumed (stream order)

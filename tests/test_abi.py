@@ -66,8 +66,8 @@ def test_argument_errors_return_before_any_device_work(lib):
     assert lib.pl_shp_select(fake, fake, 8, 8, 10.0, _w(1, 1, 1, 1), 1e-3, None, fake, None, None) == 1
     # N outside 1..32
     assert lib.pl_estimate_coherence(fake, 33, 8, 8, _w(1, 1, 1, 1), fake, 0, fake, None) == 3
-    assert lib.pl_phase_link(fake, 0, 10, 0, 0, fake, None, None, None, None) == 3
-    assert lib.pl_phase_link(None, 5, 0, 0, 0, None, None, None, None, None) == 0
+    assert lib.pl_phase_link(fake, 0, 10, 0, 0, fake, None, None, None, None, None) == 3
+    assert lib.pl_phase_link(None, 5, 0, 0, 0, None, None, None, None, None, None) == 0
     assert lib.pl_amplitude_stats(fake, 40, 4, 4, fake, fake, None) == 3
     # bad window / shapes
     assert lib.pl_shp_select(fake, fake, 8, 8, 10.0, _w(-1, 1, 1, 1), 1e-3, fake, fake, None, None) == 2
@@ -75,14 +75,27 @@ def test_argument_errors_return_before_any_device_work(lib):
     # bad scalars
     assert lib.pl_shp_select(fake, fake, 8, 8, 0.0, _w(1, 1, 1, 1), 1e-3, fake, fake, None, None) == 1
     assert lib.pl_shp_select(fake, fake, 8, 8, 5.0, _w(1, 1, 1, 1), 1.5, fake, fake, None, None) == 1
-    assert lib.pl_phase_link(fake, 5, 10, 5, 0, fake, None, None, None, None) == 1
-    assert lib.pl_phase_link(fake, 5, 10, 0, 7, fake, None, None, None, None) == 1
+    assert lib.pl_phase_link(fake, 5, 10, 5, 0, fake, None, None, None, None, None) == 1
+    assert lib.pl_phase_link(fake, 5, 10, 0, 7, fake, None, None, None, None, None) == 1
     assert lib.pl_estimate_coherence(fake, 5, 8, 8, _w(1, 1, 1, 1), fake, 9, fake, None) == 1
     assert lib.pl_compress_ministack(fake, 5, 5, 8, 8, _w(1, 1, 1, 1), fake, fake, None) == 1
+    # adjoint: workspace size, too-small workspace, bad reference
+    n = ctypes.c_size_t()
+    assert lib.pl_phase_link_vjp_workspace(20, 64, 64, _w(7, 7, 1, 1), ctypes.byref(n)) == 0
+    P, N = 64 * 64, 20
+    assert n.value >= P * N * N * 8 + P * N * 4 + P * (N * (N + 1) // 2) * 8
+    assert lib.pl_phase_link_vjp(fake, 20, 64, 64, _w(7, 7, 1, 1), fake, fake, 0, 0, fake, fake, fake,
+                                 n.value - 1, None) == 5
+    assert lib.pl_phase_link_vjp(fake, 20, 64, 64, _w(7, 7, 1, 1), fake, fake, 20, 0, fake, fake, fake,
+                                 n.value, None) == 1
+    assert lib.pl_phase_link_vjp(fake, 40, 64, 64, _w(7, 7, 1, 1), fake, fake, 0, 0, fake, fake, fake,
+                                 n.value, None) == 3
+    assert lib.pl_phase_link_vjp(None, 20, 64, 64, _w(7, 7, 1, 1), fake, fake, 0, 0, fake, fake, fake,
+                                 n.value, None) == 1
     w = (ctypes.c_double * 2)(1.0, -1.0)
     assert lib.pl_merge_amplitude_stats(fake, fake, w, 2, 4, 4, fake, fake, None) == 1
     # empty pixel list is a no-op
-    assert lib.pl_phase_link(fake, 5, 0, 0, 0, fake, None, None, None, None) == 0
+    assert lib.pl_phase_link(fake, 5, 0, 0, 0, fake, None, None, None, None, None) == 0
     assert "ref_idx" in lib.pl_last_error().decode() or lib.pl_last_error() is not None
 
 
