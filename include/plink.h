@@ -235,6 +235,46 @@ pl_status pl_seq_save(const pl_seq* s, void* host_buf, size_t bytes, pl_stream s
 /* Restores a checkpoint written by a driver with the same parameters. */
 pl_status pl_seq_load(pl_seq* s, const void* host_buf, size_t bytes, pl_stream stream);
 
+/* ------------------------------------------- batched, graph-replayed runs
+ * Several independent mini-stacks, for instance the next mini-stack of many
+ * bursts, each with its own number of compressed SLCs and hence its own N,
+ * go through the whole path of Sec. 2.2 / 3.1 / 3.2 (amplitude statistics,
+ * GLRT SHPs, sample coherence, EMI/EVD linking, compressed SLC) with one
+ * persistent launch per stage and kernel variant: each launch strides over
+ * the workgroups of all the items that share its variant.  pl_batch_plan
+ * checks the items, allocates the intermediates (SHP masks, coherence,
+ * statistics when not supplied) on the current device and, with autotune,
+ * times a few strip widths / rows per workgroup of the coherence kernel and
+ * grid sizes of the linking kernel on the items' current contents (so fill
+ * the inputs first) and keeps the fastest.  The first pl_batch_run on a stream
+ * captures the launches into a HIP graph; later runs replay it, so every
+ * pointer of the plan must stay valid and inputs are refilled in place.
+ * Results are identical to the single-call entry points. */
+typedef struct {
+    const pl_c64* stack;  /* [N][R][C]: first_real compressed SLCs, then real images */
+    int64_t R, C;
+    int32_t N;            /* 1..PL_MAX_N */
+    int32_t first_real;   /* 0..N-1 */
+    int32_t ref_idx;      /* reference image, 0..N-1 */
+    const double* mean;   /* [R][C] amplitude mean and variance for the GLRT, or */
+    const double* var;    /* NULL: computed from the real images */
+    double n_eff;         /* GLRT sample count; <= 0: N - first_real */
+    pl_c64* phasors;      /* [N][oR][oC] out */
+    uint8_t* flags;       /* [oR*oC] out, or NULL */
+    pl_c64* kappa;        /* [R][C] compressed SLC out, or NULL */
+} pl_batch_item;
+
+typedef struct pl_batch pl_batch;
+
+pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w, double alpha,
+                        pl_precision prec, pl_link_method method, int32_t autotune,
+                        pl_stream stream, pl_batch** out);
+pl_status pl_batch_run(pl_batch* b, pl_stream stream);
+pl_status pl_batch_destroy(pl_batch* b);
+/* Text summary of the plan: launches, kernel variants, tiles, grid sizes and
+ * (after a run) whether a graph is held.  Writes at most len bytes. */
+pl_status pl_batch_describe(const pl_batch* b, char* buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

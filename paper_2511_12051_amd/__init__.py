@@ -20,7 +20,7 @@ __all__ = [
     "PlinkError", "load", "library_path", "output_grid", "mask_words", "amplitude_stats",
     "merge_amplitude_stats", "shp_select", "estimate_coherence", "phase_link",
     "compress_ministack", "Sequential", "new_counters", "phase_link_vjp", "phase_link_vjp_workspace",
-    "PhaseLink", "COUNTERS", "FLAG_EMI", "FLAG_EVD",
+    "PhaseLink", "Batch", "COUNTERS", "FLAG_EMI", "FLAG_EVD",
     "FLAG_INVALID", "MAX_N",
 ]
 
@@ -53,6 +53,13 @@ class _SeqParams(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("stack", ctypes.c_void_p), ("R", ctypes.c_int64), ("C", ctypes.c_int64),
+                ("N", ctypes.c_int32), ("first_real", ctypes.c_int32), ("ref_idx", ctypes.c_int32),
+                ("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("n_eff", ctypes.c_double),
+                ("phasors", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("kappa", ctypes.c_void_p)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -72,6 +79,11 @@ _SIGNATURES = {
     "pl_phase_link_vjp": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, _P, _I32, ctypes.c_int, _P, _P,
                                          _P, ctypes.c_size_t, _P]),
     "pl_compress_ministack": (ctypes.c_int, [_P, _I32, _I32, _I64, _I64, _Window, _P, _P, _P]),
+    "pl_batch_plan": (ctypes.c_int, [ctypes.POINTER(_BatchItem), _I32, _Window, _D, ctypes.c_int, ctypes.c_int,
+                                     _I32, _P, ctypes.POINTER(_P)]),
+    "pl_batch_run": (ctypes.c_int, [_P, _P]),
+    "pl_batch_destroy": (ctypes.c_int, [_P]),
+    "pl_batch_describe": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "pl_seq_create": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(_P)]),
     "pl_seq_destroy": (ctypes.c_int, [_P]),
     "pl_seq_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
@@ -294,6 +306,71 @@ def compress_ministack(stack: torch.Tensor, first_real: int, window, phasors: to
                                         _ptr(phasors), _ptr(kappa), _stream(stack)),
            "compress_ministack")
     return kappa
+
+
+class Batch:
+    """Independent mini-stacks run together: one persistent launch per stage
+    and kernel variant, captured into a HIP graph on the first run and
+    replayed afterwards.  Each item is a dict with ``stack`` (complex64
+    [N,R,C], compressed planes first), optional ``first_real`` (0), ``ref``
+    (0), ``mean``/``var`` (float64 [R,C] statistics for the GLRT; computed
+    from the real images when absent), ``n_eff`` and ``kappa`` (True: also
+    produce the compressed SLC).  Inputs must stay where they are: refill the
+    stacks in place between runs.  Outputs: ``phasors[k]`` [N,oR,oC],
+    ``flags[k]`` [oR*oC], ``kappa[k]`` [R,C] or None."""
+
+    def __init__(self, items, window, alpha=1e-3, precision="fp32", method="emi", autotune=False):
+        lib = load()
+        self._keep, self.phasors, self.flags, self.kappa = [], [], [], []
+        arr = (_BatchItem * len(items))()
+        dev = None
+        for k, it in enumerate(items):
+            z = it["stack"]
+            _need(z, torch.complex64, 3, "Batch stack")
+            dev = z.device
+            N, R, C = z.shape
+            oR, oC = output_grid(R, C, window)
+            ph = torch.empty((N, oR, oC), dtype=torch.complex64, device=z.device)
+            fl = torch.empty((oR * oC,), dtype=torch.uint8, device=z.device)
+            kap = torch.empty((R, C), dtype=torch.complex64, device=z.device) if it.get("kappa", True) else None
+            mean, var = it.get("mean"), it.get("var")
+            for t, nm in ((mean, "mean"), (var, "var")):
+                if t is not None:
+                    _need(t, torch.float64, 2, f"Batch {nm}")
+            self._keep += [z, mean, var]
+            self.phasors.append(ph)
+            self.flags.append(fl)
+            self.kappa.append(kap)
+            arr[k] = _BatchItem(z.data_ptr(), R, C, N, int(it.get("first_real", 0)), int(it.get("ref", 0)),
+                                mean.data_ptr() if mean is not None else None,
+                                var.data_ptr() if var is not None else None, float(it.get("n_eff", 0.0)),
+                                ph.data_ptr(), fl.data_ptr(), kap.data_ptr() if kap is not None else None)
+        self._device = dev
+        h = _P()
+        _check(lib.pl_batch_plan(arr, len(items), _win(window), float(alpha), _PREC[precision],
+                                 _METHOD[method], 1 if autotune else 0,
+                                 _P(torch.cuda.current_stream(dev).cuda_stream), ctypes.byref(h)),
+               "Batch plan")
+        self._h = h
+
+    def run(self):
+        _check(load().pl_batch_run(self._h, _P(torch.cuda.current_stream(self._device).cuda_stream)), "Batch run")
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(8192)
+        _check(load().pl_batch_describe(self._h, buf, len(buf)), "Batch describe")
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().pl_batch_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass

@@ -18,8 +18,11 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libplink.so")
 ARCH = "gfx950"
 
-# Packed FP32 instructions are kept out of every kernel; no fast-math.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions are kept out of every kernel; no fast-math.  A
+# multiply and an add are fused only where they meet in one expression, so the
+# rounding of a kernel body does not depend on the code it is inlined into
+# (the single-call and batched kernels share their bodies bit for bit).
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on"]
 
 
 def hipcc() -> str:

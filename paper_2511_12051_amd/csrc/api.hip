@@ -60,6 +60,12 @@ size_t max_lds_bytes() {
     return v > 0 ? (size_t)v : 65536;
 }
 
+pl_status allow_dynamic_lds(const void* fn, size_t lds) {
+    if (lds <= 65536) return PL_OK;
+    return hip_ok(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                  "dynamic LDS attribute");
+}
+
 }  // namespace plk
 
 using namespace plk;

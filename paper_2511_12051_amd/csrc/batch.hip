@@ -1,0 +1,501 @@
+// Batched runs of the whole path over independent mini-stacks, one persistent
+// launch per stage and kernel variant, captured once into a HIP graph and
+// replayed (host side; the kernels' batched wrappers live with each stage).
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "batch_device.hpp"
+#include "internal.hpp"
+
+using namespace plk;
+
+namespace {
+
+template <typename Args>
+struct Group {
+    std::vector<int> members;     // item indices
+    std::vector<Args> args;       // per member
+    std::vector<int64_t> starts;  // members + 1 block offsets
+    Args* d_args = nullptr;
+    int64_t* d_starts = nullptr;
+    int variant = 0;    // stats: 16-byte loads; coherence: tile; linking: (N + 3) / 4
+    int threads = 0;
+    size_t lds = 0;
+    int64_t grid = 0;
+    int mult = 4;       // persistent grid = mult x (resident workgroups per CU) x CUs; 0: one per block
+    int txo = 16, rows = 0;  // coherence tile
+    float best_ms = -1.f;
+
+    bool empty() const { return members.empty(); }
+    int64_t total() const { return starts.empty() ? 0 : starts.back(); }
+    BatchRange<Args> range() const { return BatchRange<Args>{d_args, d_starts, (int)args.size(), total()}; }
+};
+
+template <typename Args>
+void add_member(Group<Args>& g, int item, const Args& a, int64_t blocks) {
+    if (g.starts.empty()) g.starts.push_back(0);
+    g.members.push_back(item);
+    g.args.push_back(a);
+    g.starts.push_back(g.starts.back() + blocks);
+}
+
+template <typename Args>
+pl_status upload(Group<Args>& g) {
+    if (g.empty()) return PL_OK;
+    if (!g.d_args) {
+        pl_status st = hip_ok(hipMalloc(&g.d_args, sizeof(Args) * g.args.size()), "pl_batch_plan: item table");
+        if (st != PL_OK) return st;
+        st = hip_ok(hipMalloc(&g.d_starts, sizeof(int64_t) * g.starts.size()), "pl_batch_plan: item table");
+        if (st != PL_OK) return st;
+    }
+    pl_status st = hip_ok(hipMemcpy(g.d_args, g.args.data(), sizeof(Args) * g.args.size(), hipMemcpyHostToDevice),
+                          "pl_batch_plan: item table upload");
+    if (st != PL_OK) return st;
+    return hip_ok(hipMemcpy(g.d_starts, g.starts.data(), sizeof(int64_t) * g.starts.size(), hipMemcpyHostToDevice),
+                  "pl_batch_plan: item table upload");
+}
+
+template <typename Args>
+void release(Group<Args>& g) {
+    if (g.d_args) (void)hipFree(g.d_args);
+    if (g.d_starts) (void)hipFree(g.d_starts);
+    g.d_args = nullptr;
+    g.d_starts = nullptr;
+}
+
+}  // namespace
+
+struct pl_batch {
+    std::vector<pl_batch_item> items;
+    std::vector<Geometry> geo;
+    std::vector<void*> allocations;
+    Group<StatsArgs> stats[2];   // [0] plain loads, [1] 16-byte loads
+    Group<GlrtArgs> glrt;
+    Group<CohArgs> coh[2];       // [0] 16-row tile, [1] 32-row tile
+    Group<LinkArgs> link[9];     // by (N + 3) / 4
+    Group<CompressArgs> comp;
+    bool split = false;
+    int cus = 1;
+    hipStream_t own = nullptr;   // capture / replay stream (default priority)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int runs = 0;
+};
+
+namespace {
+
+// persistent grid of a group: resident workgroups per CU x CUs x mult,
+// never more than the group's blocks
+template <typename Args>
+pl_status size_grid(const pl_batch* b, Group<Args>& g, const void* fn) {
+    if (g.empty()) return PL_OK;
+    const int64_t total = g.total();
+    if (g.mult <= 0) {
+        g.grid = total;
+    } else {
+        int per_cu = 0;
+        pl_status st = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, g.threads, g.lds),
+                              "pl_batch_plan: occupancy query");
+        if (st != PL_OK) return st;
+        if (per_cu < 1) per_cu = 1;
+        g.grid = (int64_t)per_cu * b->cus * g.mult;
+    }
+    if (g.grid > total) g.grid = total;
+    if (g.grid < 1) g.grid = 1;
+    if (g.grid > 2147483647LL) g.grid = 2147483647LL;
+    return PL_OK;
+}
+
+pl_status configure_coherence(pl_batch* b, int v, int txo, int rows) {
+    Group<CohArgs>& g = b->coh[v];
+    g.starts.assign(1, 0);
+    g.lds = 0;
+    for (size_t m = 0; m < g.members.size(); ++m) {
+        int64_t blocks = 0;
+        const size_t lds = coherence_args(&g.args[m], g.variant, b->split, txo, rows, &blocks);
+        if (!lds) return fail(PL_ERR_UNSUPPORTED, "pl_batch_plan: window too large for the coherence tile");
+        if (lds > g.lds) g.lds = lds;
+        g.starts.push_back(g.starts.back() + blocks);
+    }
+    g.txo = txo;
+    g.rows = rows;
+    pl_status st = allow_dynamic_lds(coherence_batch_fn(g.variant, b->split), g.lds);
+    if (st != PL_OK) return st;
+    st = size_grid(b, g, coherence_batch_fn(g.variant, b->split));
+    if (st != PL_OK) return st;
+    return upload(g);
+}
+
+pl_status enqueue_front(pl_batch* b, hipStream_t s) {  // statistics and GLRT
+    for (int v = 0; v < 2; ++v) {
+        if (b->stats[v].empty()) continue;
+        pl_status st = launch_amp_stats_batch(b->stats[v].range(), v == 1, b->stats[v].grid, s);
+        if (st != PL_OK) return st;
+    }
+    return launch_shp_select_batch(b->glrt.range(), b->glrt.threads, b->glrt.lds, b->glrt.grid, s);
+}
+
+pl_status enqueue_coherence(pl_batch* b, hipStream_t s) {
+    for (int v = 0; v < 2; ++v) {
+        if (b->coh[v].empty()) continue;
+        pl_status st = launch_coherence_batch(b->coh[v].range(), b->coh[v].variant, b->split, b->coh[v].lds,
+                                              b->coh[v].grid, s);
+        if (st != PL_OK) return st;
+    }
+    return PL_OK;
+}
+
+pl_status enqueue_link(pl_batch* b, hipStream_t s) {
+    for (auto& g : b->link) {
+        if (g.empty()) continue;
+        pl_status st = launch_phase_link_batch(g.range(), g.variant, g.grid, s);
+        if (st != PL_OK) return st;
+    }
+    return PL_OK;
+}
+
+pl_status enqueue_all(pl_batch* b, hipStream_t s) {
+    pl_status st = enqueue_front(b, s);
+    if (st == PL_OK) st = enqueue_coherence(b, s);
+    if (st == PL_OK) st = enqueue_link(b, s);
+    if (st == PL_OK && !b->comp.empty()) st = launch_compress_batch(b->comp.range(), b->comp.grid, s);
+    return st;
+}
+
+// average device time of fn over reps launches after one warm-up
+template <typename F>
+pl_status time_ms(hipStream_t s, F fn, int reps, float* ms) {
+    hipEvent_t e0, e1;
+    pl_status st = hip_ok(hipEventCreate(&e0), "pl_batch_plan: event");
+    if (st != PL_OK) return st;
+    st = hip_ok(hipEventCreate(&e1), "pl_batch_plan: event");
+    if (st != PL_OK) {
+        (void)hipEventDestroy(e0);
+        return st;
+    }
+    st = fn();
+    if (st == PL_OK) st = hip_ok(hipEventRecord(e0, s), "pl_batch_plan: event");
+    for (int r = 0; r < reps && st == PL_OK; ++r) st = fn();
+    if (st == PL_OK) st = hip_ok(hipEventRecord(e1, s), "pl_batch_plan: event");
+    if (st == PL_OK) st = hip_ok(hipEventSynchronize(e1), "pl_batch_plan: autotune run");
+    if (st == PL_OK) st = hip_ok(hipEventElapsedTime(ms, e0, e1), "pl_batch_plan: event");
+    *ms /= (float)reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+pl_status autotune(pl_batch* b) {
+    hipStream_t s = b->own;
+    pl_status st = enqueue_front(b, s);  // SHP masks of the current inputs
+    if (st != PL_OK) return st;
+    static const int tiles[][2] = {{16, 0}, {8, 0}, {16, 2}, {16, 8}, {4, 0}};
+    for (int v = 0; v < 2; ++v) {
+        Group<CohArgs>& g = b->coh[v];
+        if (g.empty()) continue;
+        float best = 0.f;
+        int bt = 16, br = 0, bm = 4;
+        for (int mult : {4, 0}) {
+            for (auto& t : tiles) {
+                g.mult = mult;
+                st = configure_coherence(b, v, t[0], t[1]);
+                if (st != PL_OK) return st;
+                float ms = 0.f;
+                st = time_ms(s, [&] { return launch_coherence_batch(g.range(), g.variant, b->split, g.lds, g.grid, s); },
+                             2, &ms);
+                if (st != PL_OK) return st;
+                if (best == 0.f || ms < best) {
+                    best = ms;
+                    bt = t[0];
+                    br = t[1];
+                    bm = mult;
+                }
+            }
+        }
+        g.mult = bm;
+        st = configure_coherence(b, v, bt, br);
+        if (st != PL_OK) return st;
+        g.best_ms = best;
+    }
+    st = enqueue_coherence(b, s);  // coherence of the current inputs for the linking runs
+    if (st != PL_OK) return st;
+    for (auto& g : b->link) {
+        if (g.empty()) continue;
+        float best = 0.f;
+        int bm = g.mult;
+        for (int mult : {1, 2, 4, 0}) {
+            g.mult = mult;
+            st = size_grid(b, g, phase_link_batch_fn(g.variant));
+            if (st != PL_OK) return st;
+            float ms = 0.f;
+            st = time_ms(s, [&] { return launch_phase_link_batch(g.range(), g.variant, g.grid, s); }, 2, &ms);
+            if (st != PL_OK) return st;
+            if (best == 0.f || ms < best) {
+                best = ms;
+                bm = mult;
+            }
+        }
+        g.mult = bm;
+        st = size_grid(b, g, phase_link_batch_fn(g.variant));
+        if (st != PL_OK) return st;
+        g.best_ms = best;
+    }
+    return hip_ok(hipStreamSynchronize(s), "pl_batch_plan: autotune");
+}
+
+void destroy(pl_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto& g : b->stats) release(g);
+    release(b->glrt);
+    for (auto& g : b->coh) release(g);
+    for (auto& g : b->link) release(g);
+    release(b->comp);
+    for (void* p : b->allocations) (void)hipFree(p);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->own) (void)hipStreamDestroy(b->own);
+    delete b;
+}
+
+}  // namespace
+
+#define PL_CHECK(cond, status, ...) \
+    do {                            \
+        if (!(cond)) return fail(status, __VA_ARGS__); \
+    } while (0)
+
+extern "C" {
+
+pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w, double alpha,
+                        pl_precision prec, pl_link_method method, int32_t tune, pl_stream stream,
+                        pl_batch** out) {
+    PL_CHECK(items && out, PL_ERR_INVALID_ARG, "pl_batch_plan: NULL pointer");
+    PL_CHECK(n_items >= 1 && n_items <= 4096, PL_ERR_UNSUPPORTED, "pl_batch_plan: %d items (1..4096)", n_items);
+    PL_CHECK(alpha > 0 && alpha < 1, PL_ERR_INVALID_ARG, "pl_batch_plan: alpha must lie in (0, 1)");
+    PL_CHECK(prec == PL_PREC_FP32 || prec == PL_PREC_SPLIT_BF16, PL_ERR_INVALID_ARG,
+             "pl_batch_plan: unknown precision %d", (int)prec);
+    PL_CHECK(method == PL_LINK_EMI || method == PL_LINK_EVD, PL_ERR_INVALID_ARG,
+             "pl_batch_plan: unknown method %d", (int)method);
+    for (int k = 0; k < n_items; ++k) {
+        const pl_batch_item& it = items[k];
+        Geometry g;
+        PL_CHECK(it.stack && it.phasors, PL_ERR_INVALID_ARG, "pl_batch_plan: item %d: NULL stack or phasors", k);
+        PL_CHECK(it.N >= 1 && it.N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_batch_plan: item %d: N=%d outside 1..%d", k,
+                 it.N, kMaxN);
+        PL_CHECK(it.first_real >= 0 && it.first_real < it.N, PL_ERR_INVALID_ARG,
+                 "pl_batch_plan: item %d: first_real %d outside 0..%d", k, it.first_real, it.N - 1);
+        PL_CHECK(it.ref_idx >= 0 && it.ref_idx < it.N, PL_ERR_INVALID_ARG,
+                 "pl_batch_plan: item %d: ref_idx %d outside 0..%d", k, it.ref_idx, it.N - 1);
+        PL_CHECK((it.mean == nullptr) == (it.var == nullptr), PL_ERR_INVALID_ARG,
+                 "pl_batch_plan: item %d: mean and var must both be given or both be NULL", k);
+        PL_CHECK(make_geometry(it.R, it.C, w, &g) && g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE,
+                 "pl_batch_plan: item %d: bad image size or window", k);
+        PL_CHECK(g.R <= 2147483647LL, PL_ERR_UNSUPPORTED, "pl_batch_plan: item %d: too many rows", k);
+    }
+    pl_batch* b = new pl_batch();
+    b->split = prec == PL_PREC_SPLIT_BF16;
+    pl_status st = PL_OK;
+    auto bail = [&](pl_status s) {
+        destroy(b);
+        return s;
+    };
+    {
+        int dev = 0;
+        st = hip_ok(hipGetDevice(&dev), "pl_batch_plan: device");
+        if (st == PL_OK) st = hip_ok(hipDeviceGetAttribute(&b->cus, hipDeviceAttributeMultiprocessorCount, dev),
+                                     "pl_batch_plan: device attribute");
+        if (st == PL_OK) st = hip_ok(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking), "pl_batch_plan: stream");
+        if (st == PL_OK) st = hip_ok(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming), "pl_batch_plan: event");
+        if (st == PL_OK) st = hip_ok(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming), "pl_batch_plan: event");
+        if (st != PL_OK) return bail(st);
+    }
+    b->items.assign(items, items + n_items);
+    for (int k = 0; k < n_items; ++k) {
+        const pl_batch_item& it = items[k];
+        Geometry g;
+        make_geometry(it.R, it.C, w, &g);
+        b->geo.push_back(g);
+        const int64_t P = g.oR * g.oC, px = g.R * g.C;
+        auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+        const size_t o_mask = 0, o_count = up(o_mask + (size_t)P * g.nw * 4), o_coh = up(o_count + (size_t)P * 2);
+        const size_t o_mean = up(o_coh + (size_t)P * it.N * it.N * 8);
+        const size_t o_var = o_mean + (it.mean ? 0 : up((size_t)px * 8));
+        const size_t bytes = o_var + (it.mean ? 0 : up((size_t)px * 8));
+        void* mem = nullptr;
+        st = hip_ok(hipMalloc(&mem, bytes), "pl_batch_plan: intermediates");
+        if (st != PL_OK) return bail(st);
+        b->allocations.push_back(mem);
+        unsigned char* base = static_cast<unsigned char*>(mem);
+        uint32_t* mask = reinterpret_cast<uint32_t*>(base + o_mask);
+        uint16_t* count = reinterpret_cast<uint16_t*>(base + o_count);
+        float2* coh = reinterpret_cast<float2*>(base + o_coh);
+        const double* mean = it.mean;
+        const double* var = it.var;
+        const PlaneTable t = contiguous_planes(it.stack, it.N, px);
+        if (!mean) {
+            double* m = reinterpret_cast<double*>(base + o_mean);
+            double* v = reinterpret_cast<double*>(base + o_var);
+            StatsArgs a;
+            int64_t blocks;
+            const bool vec = stats_args(t, it.first_real, it.N - it.first_real, px, m, v, &a, &blocks);
+            add_member(b->stats[vec ? 1 : 0], k, a, blocks);
+            mean = m;
+            var = v;
+        }
+        {
+            GlrtArgs a;
+            int64_t blocks;
+            size_t lds;
+            const double n_eff = it.n_eff > 0 ? it.n_eff : (double)(it.N - it.first_real);
+            if (!glrt_args(mean, var, g, n_eff, alpha, mask, count, nullptr, &a, &blocks, &lds))
+                return bail(fail(PL_ERR_UNSUPPORTED, "pl_batch_plan: window/stride too large for the GLRT tile"));
+            add_member(b->glrt, k, a, blocks);
+            b->glrt.threads = a.TX * a.TY;  // same window and stride for every item
+            b->glrt.lds = lds;
+        }
+        {
+            CohArgs a{};
+            a.t = t;
+            a.N = it.N;
+            a.g = g;
+            a.mask = mask;
+            a.coh = coh;
+            a.n_pairs = g.wy * (g.hx + 1);
+            Group<CohArgs>& cg = b->coh[it.N <= 16 ? 0 : 1];
+            cg.variant = it.N <= 16 ? 16 : 32;
+            add_member(cg, k, a, 0);  // blocks set by configure_coherence
+        }
+        {
+            LinkArgs a{coh, it.N, P, it.ref_idx, (int)method, reinterpret_cast<float2*>(it.phasors), nullptr,
+                       nullptr, it.flags, nullptr};
+            Group<LinkArgs>& lg = b->link[(it.N + 3) / 4];
+            lg.variant = (it.N + 3) / 4;
+            add_member(lg, k, a, link_blocks(it.N, P));
+        }
+        if (it.kappa) {
+            int64_t blocks;
+            const CompressArgs a = compress_args(t, it.N, it.first_real, g, reinterpret_cast<const float2*>(it.phasors),
+                                                 reinterpret_cast<float2*>(it.kappa), &blocks);
+            add_member(b->comp, k, a, blocks);
+        }
+    }
+    for (int v = 0; v < 2; ++v) {
+        b->stats[v].threads = 256;
+        if ((st = size_grid(b, b->stats[v], amp_stats_batch_fn(v == 1))) != PL_OK) return bail(st);
+        if ((st = upload(b->stats[v])) != PL_OK) return bail(st);
+    }
+    if ((st = allow_dynamic_lds(glrt_batch_fn(), b->glrt.lds)) != PL_OK) return bail(st);
+    if ((st = size_grid(b, b->glrt, glrt_batch_fn())) != PL_OK) return bail(st);
+    if ((st = upload(b->glrt)) != PL_OK) return bail(st);
+    for (int v = 0; v < 2; ++v) {
+        Group<CohArgs>& g = b->coh[v];
+        if (g.empty()) continue;
+        g.threads = 64 * 8;
+        if ((st = configure_coherence(b, v, 16, 0)) != PL_OK) return bail(st);
+    }
+    for (auto& g : b->link) {
+        if (g.empty()) continue;
+        g.threads = 256;
+        if ((st = size_grid(b, g, phase_link_batch_fn(g.variant))) != PL_OK) return bail(st);
+        if ((st = upload(g)) != PL_OK) return bail(st);
+    }
+    b->comp.threads = 256;
+    if ((st = size_grid(b, b->comp, compress_batch_fn())) != PL_OK) return bail(st);
+    if ((st = upload(b->comp)) != PL_OK) return bail(st);
+    if (tune) {
+        // inputs written on the caller's stream are visible to the plan's stream
+        st = hip_ok(hipEventRecord(b->ev_in, reinterpret_cast<hipStream_t>(stream)), "pl_batch_plan: event");
+        if (st == PL_OK) st = hip_ok(hipStreamWaitEvent(b->own, b->ev_in, 0), "pl_batch_plan: event");
+        if (st == PL_OK) st = autotune(b);
+        if (st != PL_OK) return bail(st);
+    }
+    *out = b;
+    return PL_OK;
+}
+
+pl_status pl_batch_run(pl_batch* b, pl_stream stream) {
+    PL_CHECK(b, PL_ERR_INVALID_ARG, "pl_batch_run: NULL plan");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    pl_status st = hip_ok(hipEventRecord(b->ev_in, s), "pl_batch_run: event");
+    if (st == PL_OK) st = hip_ok(hipStreamWaitEvent(b->own, b->ev_in, 0), "pl_batch_run: event");
+    if (st != PL_OK) return st;
+    if (!b->exec) {
+        st = hip_ok(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal), "pl_batch_run: graph capture");
+        if (st != PL_OK) return st;
+        const pl_status launched = enqueue_all(b, b->own);
+        hipGraph_t graph = nullptr;
+        st = hip_ok(hipStreamEndCapture(b->own, &graph), "pl_batch_run: graph capture");
+        if (launched != PL_OK || st != PL_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return launched != PL_OK ? launched : st;
+        }
+        b->graph = graph;
+        st = hip_ok(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "pl_batch_run: graph instantiate");
+        if (st != PL_OK) return st;
+    }
+    st = hip_ok(hipGraphLaunch(b->exec, b->own), "pl_batch_run: graph launch");
+    if (st == PL_OK) st = hip_ok(hipEventRecord(b->ev_out, b->own), "pl_batch_run: event");
+    if (st == PL_OK) st = hip_ok(hipStreamWaitEvent(s, b->ev_out, 0), "pl_batch_run: event");
+    if (st == PL_OK) ++b->runs;
+    return st;
+}
+
+pl_status pl_batch_destroy(pl_batch* b) {
+    if (!b) return PL_OK;
+    (void)hipStreamSynchronize(b->own);
+    destroy(b);
+    return PL_OK;
+}
+
+pl_status pl_batch_describe(const pl_batch* b, char* buf, size_t len) {
+    PL_CHECK(b && buf && len > 0, PL_ERR_INVALID_ARG, "pl_batch_describe: NULL pointer");
+    std::string s;
+    char line[256];
+    snprintf(line, sizeof line, "items %zu, CUs %d, runs %d, graph %s\n", b->items.size(), b->cus, b->runs,
+             b->exec ? "captured" : "not yet");
+    s += line;
+    int launches = 0;
+    for (int v = 0; v < 2; ++v)
+        if (!b->stats[v].empty()) {
+            ++launches;
+            snprintf(line, sizeof line, "stats%s: %zu items, %lld blocks, grid %lld\n", v ? " (16-byte)" : "",
+                     b->stats[v].members.size(), (long long)b->stats[v].total(), (long long)b->stats[v].grid);
+            s += line;
+        }
+    ++launches;
+    snprintf(line, sizeof line, "glrt: %zu items, %lld blocks, grid %lld\n", b->glrt.members.size(),
+             (long long)b->glrt.total(), (long long)b->glrt.grid);
+    s += line;
+    for (auto& g : b->coh)
+        if (!g.empty()) {
+            ++launches;
+            snprintf(line, sizeof line,
+                     "coherence tile %d%s: %zu items, strip %d, rows %d, %lld blocks, grid %lld, lds %zu, tuned %.3f ms\n",
+                     g.variant, b->split ? " split-bf16" : " fp32", g.members.size(), g.txo, g.args[0].rows_per_wg,
+                     (long long)g.total(), (long long)g.grid, g.lds, g.best_ms);
+            s += line;
+        }
+    for (auto& g : b->link)
+        if (!g.empty()) {
+            ++launches;
+            snprintf(line, sizeof line, "link N<=%d: %zu items, %lld blocks, grid %lld (x%d), tuned %.3f ms\n",
+                     4 * g.variant, g.members.size(), (long long)g.total(), (long long)g.grid, g.mult, g.best_ms);
+            s += line;
+        }
+    if (!b->comp.empty()) {
+        ++launches;
+        snprintf(line, sizeof line, "compress: %zu items, %lld blocks, grid %lld\n", b->comp.members.size(),
+                 (long long)b->comp.total(), (long long)b->comp.grid);
+        s += line;
+    }
+    snprintf(line, sizeof line, "launches per run %d\n", launches);
+    s += line;
+    snprintf(buf, len, "%s", s.c_str());
+    return PL_OK;
+}
+
+}  // extern "C"

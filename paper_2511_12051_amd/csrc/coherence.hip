@@ -32,6 +32,7 @@
 // 16-byte LDS read per pair.
 #include <cmath>
 
+#include "batch_device.hpp"
 #include "internal.hpp"
 
 namespace plk {
@@ -47,23 +48,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 #endif
 constexpr int kMaxWaves = PL_COH_WAVES;  // wavefronts per workgroup (one workgroup per CU)
 
-struct CohArgs {
-    PlaneTable t;
-    int N;
-    Geometry g;
-    const uint32_t* mask;
-    float2* coh;
-    float* diag;      // optional [P][N] diagonal of A (SHP-summed |z|^2), or null
-    int TXo;          // output columns per strip
-    int rows_per_wg;  // output rows per workgroup
-    int tile_w;       // staged input columns (even)
-    int pitch;        // records (pixel pairs) per staged row = tile_w / 2
-    int plane;        // records per image plane (wy * pitch, padded)
-    int wave_words;   // 32-bit words of LDS per wavefront
-    int n_pairs;      // pairs per window = (2 hy + 1)(hx + 1)
-    float inv_ppr;    // 1 / (hx + 1), for exact small divisions
-    int vec_rows;     // every image row starts 16-byte aligned (pairs load as 16 bytes)
-};
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -438,17 +422,15 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
 }
 
 template <int NT, bool SPLIT>
-__global__ __launch_bounds__(64 * kMaxWaves) void coherence_kernel(CohArgs a) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
+__device__ void coherence_body(const CohArgs& a, int64_t strip, int64_t band, uint32_t* lds_words) {
     const Geometry& g = a.g;
     const int nthreads = blockDim.x;
     const int nwaves = nthreads >> 6;
     const int wave = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t strip = blockIdx.x;
     const int64_t ox0 = strip * a.TXo;
     const int64_t ox1 = ox0 + a.TXo < g.oC ? ox0 + a.TXo : g.oC;
-    const int64_t oy0 = (int64_t)blockIdx.y * a.rows_per_wg;
+    const int64_t oy0 = band * a.rows_per_wg;
     const int64_t oy1 = oy0 + a.rows_per_wg < g.oR ? oy0 + a.rows_per_wg : g.oR;
     const int64_t x0 = (ox0 * g.sx + g.sx / 2 - g.hx) & ~(int64_t)1;
     const int data_words = 4 * a.N * a.plane;  // one 16-byte record per pixel pair
@@ -495,24 +477,53 @@ __global__ __launch_bounds__(64 * kMaxWaves) void coherence_kernel(CohArgs a) {
 }
 
 template <int NT, bool SPLIT>
-pl_status launch_variant(const CohArgs& a0, hipStream_t s) {
-    CohArgs a = a0;
+__global__ __launch_bounds__(64 * kMaxWaves) void coherence_kernel(CohArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
+    coherence_body<NT, SPLIT>(a, blockIdx.x, blockIdx.y, lds_words);
+}
+
+template <int NT, bool SPLIT>
+__global__ __launch_bounds__(64 * kMaxWaves) void coherence_batch(BatchRange<CohArgs> r) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
+    for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
+        const int k = batch_item(r.starts, r.n, b);
+        const CohArgs& a = r.items[k];
+        const int64_t local = b - r.starts[k];
+        // the body ends with a workgroup barrier, after which LDS may be refilled
+        coherence_body<NT, SPLIT>(a, local % a.n_strips, local / a.n_strips, lds_words);
+    }
+}
+
+template <int NT, bool SPLIT>
+const void* kernel_of(bool batch) {
+    return batch ? reinterpret_cast<const void*>(coherence_batch<NT, SPLIT>)
+                 : reinterpret_cast<const void*>(coherence_kernel<NT, SPLIT>);
+}
+
+const void* coherence_fn(int nt, bool split, bool batch) {
+    if (nt == 16) return split ? kernel_of<16, true>(batch) : kernel_of<16, false>(batch);
+    return split ? kernel_of<32, true>(batch) : kernel_of<32, false>(batch);
+}
+
+}  // namespace
+
+size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req, int64_t* blocks) {
+    CohArgs& a = *ap;
     const Geometry& g = a.g;
     const size_t lds_cap = max_lds_bytes();
-    constexpr int PPK = SPLIT ? (NT == 16 ? 16 : 8) : (NT == 16 ? 2 : 1);
-    const int scratch_words = NT * (NT + 1) + NT;
+    const int PPK = split ? (nt == 16 ? 16 : 8) : (nt == 16 ? 2 : 1);
+    const int scratch_words = nt * (nt + 1) + nt;
     const int table_words = ((2 * (a.n_pairs + PPK) + 3) / 4) * 4;
     a.wave_words = ((scratch_words > table_words ? scratch_words : table_words) + 3) / 4 * 4;
     int chosen = 0;
     size_t lds = 0;
-    for (int txo = 16; txo >= 1; --txo) {
+    for (int txo = txo_max < 16 ? txo_max : 16; txo >= 1; --txo) {
         int tile_w = (txo - 1) * g.sx + 2 * g.hx + 3;
         tile_w += tile_w & 1;
         const int pitch = tile_w >> 1;
         int plane = g.wy * pitch;
         plane += (1 - plane % 16 + 16) % 16;  // records = 1 mod 16: stride 4 mod 64 words
-        const int nw = txo < kMaxWaves ? txo : kMaxWaves;
-        const size_t bytes = (size_t)16 * a.N * plane + (size_t)nw * a.wave_words * 4;
+        const size_t bytes = (size_t)16 * a.N * plane + (size_t)kMaxWaves * a.wave_words * 4;
         if (bytes <= lds_cap) {
             chosen = txo;
             a.tile_w = tile_w;
@@ -522,36 +533,24 @@ pl_status launch_variant(const CohArgs& a0, hipStream_t s) {
             break;
         }
     }
-    if (!chosen) return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: window too large for LDS");
+    if (!chosen) return 0;
     a.TXo = chosen;
     a.inv_ppr = 1.0f / (float)(g.hx + 1);
-    const int nwaves = chosen < kMaxWaves ? chosen : kMaxWaves;
-    if ((int64_t)a.N * (a.tile_w >> 1) > (int64_t)kMaxItems * 64 * nwaves)
-        return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: strip too wide for the staging layout");
+    if ((int64_t)a.N * (a.tile_w >> 1) > (int64_t)kMaxItems * 64 * kMaxWaves) return 0;
     a.vec_rows = (g.C % 2) == 0;
     for (int d = 0; d < a.N; ++d)
         if (reinterpret_cast<uintptr_t>(a.t.p[d]) & 15) a.vec_rows = 0;
-    const int64_t n_strips = (g.oC + chosen - 1) / chosen;
-    // enough workgroups to fill the chip several times over
-    int64_t rows = (g.oR * n_strips + 2047) / 2048;
-    if (rows < 4) rows = 4;
+    a.n_strips = (g.oC + chosen - 1) / chosen;
+    int64_t rows = rows_req;
+    if (rows <= 0) {  // enough workgroups to fill the chip several times over
+        rows = (g.oR * a.n_strips + 2047) / 2048;
+        if (rows < 4) rows = 4;
+    }
     if (rows > g.oR) rows = g.oR;
     a.rows_per_wg = (int)rows;
-    const int64_t n_bands = (g.oR + rows - 1) / rows;
-    if (n_strips > 2147483647LL || n_bands > 65535)
-        return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: output grid too large");
-    auto kern = coherence_kernel<NT, SPLIT>;
-    if (lds > 65536) {
-        pl_status st = hip_ok(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
-                              "coherence kernel LDS attribute");
-        if (st != PL_OK) return st;
-    }
-    hipLaunchKernelGGL(kern, dim3((unsigned)n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
-    return launch_ok("coherence kernel");
+    *blocks = a.n_strips * ((g.oR + rows - 1) / rows);
+    return lds;
 }
-
-}  // namespace
 
 pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
                            int prec, float2* coh, float* diag, hipStream_t s) {
@@ -564,8 +563,43 @@ pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const 
     a.coh = coh;
     a.n_pairs = g.wy * (g.hx + 1);
     const bool split = prec == PL_PREC_SPLIT_BF16;
-    if (N <= 16) return split ? launch_variant<16, true>(a, s) : launch_variant<16, false>(a, s);
-    return split ? launch_variant<32, true>(a, s) : launch_variant<32, false>(a, s);
+    const int nt = N <= 16 ? 16 : 32;
+    int64_t blocks = 0;
+    const size_t lds = coherence_args(&a, nt, split, 16, 0, &blocks);
+    if (!lds) return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: window too large for LDS");
+    const int64_t n_bands = blocks / a.n_strips;
+    if (a.n_strips > 2147483647LL || n_bands > 65535)
+        return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: output grid too large");
+    const void* fn = coherence_fn(nt, split, false);
+    pl_status st = allow_dynamic_lds(fn, lds);
+    if (st != PL_OK) return st;
+    // always kMaxWaves waves: the staging layout (and its size check) assumes them
+    const int nwaves = kMaxWaves;
+    if (nt == 16) {
+        if (split) hipLaunchKernelGGL((coherence_kernel<16, true>), dim3((unsigned)a.n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
+        else hipLaunchKernelGGL((coherence_kernel<16, false>), dim3((unsigned)a.n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
+    } else {
+        if (split) hipLaunchKernelGGL((coherence_kernel<32, true>), dim3((unsigned)a.n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
+        else hipLaunchKernelGGL((coherence_kernel<32, false>), dim3((unsigned)a.n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
+    }
+    return launch_ok("coherence kernel");
+}
+
+const void* coherence_batch_fn(int nt, bool split) { return coherence_fn(nt, split, true); }
+
+// the caller has raised the kernel's dynamic LDS limit (allow_dynamic_lds)
+pl_status launch_coherence_batch(const BatchRange<CohArgs>& r, int nt, bool split, size_t lds, int64_t grid,
+                                 hipStream_t s) {
+    if (r.total == 0) return PL_OK;
+    const dim3 gr((unsigned)grid), bl(64 * kMaxWaves);
+    if (nt == 16) {
+        if (split) hipLaunchKernelGGL((coherence_batch<16, true>), gr, bl, lds, s, r);
+        else hipLaunchKernelGGL((coherence_batch<16, false>), gr, bl, lds, s, r);
+    } else {
+        if (split) hipLaunchKernelGGL((coherence_batch<32, true>), gr, bl, lds, s, r);
+        else hipLaunchKernelGGL((coherence_batch<32, false>), gr, bl, lds, s, r);
+    }
+    return launch_ok("batched coherence kernel");
 }
 
 }  // namespace plk

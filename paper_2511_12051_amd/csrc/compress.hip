@@ -2,6 +2,7 @@
 // real images, each full-resolution pixel using the linked phasors of its
 // decimation block.  HBM-bound: one thread per pixel, coalesced plane reads;
 // the phasor reads hit in cache (one block serves stride_x * stride_y pixels).
+#include "batch_device.hpp"
 #include "internal.hpp"
 
 namespace plk {
@@ -10,11 +11,13 @@ namespace {
 constexpr int kBlock = 256;
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__global__ __launch_bounds__(kBlock) void compress_kernel(PlaneTable t, int N, int first_real,
-                                                          Geometry g, const float2* __restrict__ ph,
-                                                          float2* __restrict__ kappa) {
-    const int64_t x = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t y = blockIdx.y;
+__device__ __forceinline__ void compress_body(const CompressArgs& a, int64_t block_x, int64_t y) {
+    const PlaneTable& t = a.t;
+    const Geometry& g = a.g;
+    const int N = a.N, first_real = a.first_real;
+    const float2* __restrict__ ph = a.ph;
+    float2* __restrict__ kappa = a.kappa;
+    const int64_t x = block_x * kBlock + threadIdx.x;
     if (x >= g.C) return;
     int64_t by = y / g.sy, bx = x / g.sx;
     by = by < g.oR - 1 ? by : g.oR - 1;
@@ -33,14 +36,42 @@ __global__ __launch_bounds__(kBlock) void compress_kernel(PlaneTable t, int N, i
     kappa[p] = make_float2(re, im);
 }
 
+__global__ __launch_bounds__(kBlock) void compress_kernel(CompressArgs a) { compress_body(a, blockIdx.x, blockIdx.y); }
+
+__global__ __launch_bounds__(kBlock) void compress_batch(BatchRange<CompressArgs> r) {
+    for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
+        const int k = batch_item(r.starts, r.n, b);
+        const CompressArgs& a = r.items[k];
+        const int64_t local = b - r.starts[k];
+        compress_body(a, local % a.gx, local / a.gx);
+    }
+}
+
 }  // namespace
+
+CompressArgs compress_args(const PlaneTable& t, int N, int first_real, const Geometry& g,
+                           const float2* phasors, float2* kappa, int64_t* blocks) {
+    CompressArgs a{t, N, first_real, g, phasors, kappa, (g.C + kBlock - 1) / kBlock};
+    *blocks = a.gx * g.R;
+    return a;
+}
 
 pl_status launch_compress(const PlaneTable& t, int N, int first_real, const Geometry& g,
                           const float2* phasors, float2* kappa, hipStream_t s) {
     if (g.R > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_compress_ministack: too many rows");
-    dim3 grid((unsigned)((g.C + kBlock - 1) / kBlock), (unsigned)g.R);
-    hipLaunchKernelGGL(compress_kernel, grid, dim3(kBlock), 0, s, t, N, first_real, g, phasors, kappa);
+    int64_t blocks;
+    const CompressArgs a = compress_args(t, N, first_real, g, phasors, kappa, &blocks);
+    dim3 grid((unsigned)a.gx, (unsigned)g.R);
+    hipLaunchKernelGGL(compress_kernel, grid, dim3(kBlock), 0, s, a);
     return launch_ok("compress kernel");
+}
+
+const void* compress_batch_fn() { return reinterpret_cast<const void*>(compress_batch); }
+
+pl_status launch_compress_batch(const BatchRange<CompressArgs>& r, int64_t grid, hipStream_t s) {
+    if (r.total == 0) return PL_OK;
+    hipLaunchKernelGGL(compress_batch, dim3((unsigned)grid), dim3(kBlock), 0, s, r);
+    return launch_ok("batched compress kernel");
 }
 
 }  // namespace plk

@@ -13,6 +13,7 @@
 // |T - thr| < 1e-9 are counted.
 #include <cmath>
 
+#include "batch_device.hpp"
 #include "internal.hpp"
 
 namespace plk {
@@ -21,21 +22,9 @@ namespace {
 constexpr double kRecheckRel = 1e-8;
 constexpr double kBand = 1e-9;
 
-struct GlrtArgs {
-    const double* mean;
-    const double* var;
-    Geometry g;
-    int TX, TY, tw, th;
-    double n, thr, rlo, rhi;
-    uint32_t* mask;
-    uint16_t* count;
-    unsigned long long* counters;
-};
-
-__global__ __launch_bounds__(256) void glrt_kernel(GlrtArgs a) {
-    extern __shared__ double s_tile[];
+__device__ void glrt_body(const GlrtArgs& a, int64_t bx, int64_t by, double* s_tile) {
     const Geometry& g = a.g;
-    const int64_t oy0 = (int64_t)blockIdx.y * a.TY, ox0 = (int64_t)blockIdx.x * a.TX;
+    const int64_t oy0 = by * a.TY, ox0 = bx * a.TX;
     const int64_t y0 = oy0 * g.sy + g.sy / 2 - g.hy;
     const int64_t x0 = ox0 * g.sx + g.sx / 2 - g.hx;
     const int nt = a.tw * a.th;
@@ -113,11 +102,27 @@ double chi2_1_isf(double alpha) {
     return (double)(z * z);
 }
 
+__global__ __launch_bounds__(256) void glrt_kernel(GlrtArgs a) {
+    extern __shared__ double s_tile[];
+    glrt_body(a, blockIdx.x, blockIdx.y, s_tile);
+}
+
+__global__ __launch_bounds__(256) void glrt_batch(BatchRange<GlrtArgs> r) {
+    extern __shared__ double s_tile[];
+    for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
+        const int k = batch_item(r.starts, r.n, b);
+        const GlrtArgs& a = r.items[k];
+        const int64_t local = b - r.starts[k];
+        glrt_body(a, local % a.gx, local / a.gx, s_tile);
+        __syncthreads();  // the tile is refilled by the next block
+    }
+}
+
 }  // namespace
 
-pl_status launch_shp_select(const double* mean, const double* var, const Geometry& g,
-                            double n_eff, double alpha, uint32_t* mask, uint16_t* count,
-                            unsigned long long* counters, hipStream_t s) {
+bool glrt_args(const double* mean, const double* var, const Geometry& g, double n_eff, double alpha,
+               uint32_t* mask, uint16_t* count, unsigned long long* counters, GlrtArgs* out,
+               int64_t* blocks, size_t* lds) {
     GlrtArgs a{};
     a.mean = mean;
     a.var = var;
@@ -140,12 +145,34 @@ pl_status launch_shp_select(const double* mean, const double* var, const Geometr
         a.th = (a.TY - 1) * g.sy + g.wy;
         if ((size_t)a.tw * a.th * sizeof(double) <= budget) break;
     }
-    size_t lds = (size_t)a.tw * a.th * sizeof(double);
-    if (lds > budget) return fail(PL_ERR_UNSUPPORTED, "pl_shp_select: window/stride too large for LDS");
-    dim3 grid((unsigned)((g.oC + a.TX - 1) / a.TX), (unsigned)((g.oR + a.TY - 1) / a.TY));
+    *lds = (size_t)a.tw * a.th * sizeof(double);
+    a.gx = (g.oC + a.TX - 1) / a.TX;
+    *blocks = a.gx * ((g.oR + a.TY - 1) / a.TY);
+    *out = a;
+    return *lds <= budget;
+}
+
+pl_status launch_shp_select(const double* mean, const double* var, const Geometry& g,
+                            double n_eff, double alpha, uint32_t* mask, uint16_t* count,
+                            unsigned long long* counters, hipStream_t s) {
+    GlrtArgs a;
+    int64_t blocks;
+    size_t lds;
+    if (!glrt_args(mean, var, g, n_eff, alpha, mask, count, counters, &a, &blocks, &lds))
+        return fail(PL_ERR_UNSUPPORTED, "pl_shp_select: window/stride too large for LDS");
+    dim3 grid((unsigned)a.gx, (unsigned)((g.oR + a.TY - 1) / a.TY));
     if (grid.y > 65535) return fail(PL_ERR_UNSUPPORTED, "pl_shp_select: output grid too tall");
     hipLaunchKernelGGL(glrt_kernel, grid, dim3(a.TX * a.TY), lds, s, a);
     return launch_ok("GLRT kernel");
+}
+
+const void* glrt_batch_fn() { return reinterpret_cast<const void*>(glrt_batch); }
+
+pl_status launch_shp_select_batch(const BatchRange<GlrtArgs>& r, int threads, size_t lds, int64_t grid,
+                                  hipStream_t s) {
+    if (r.total == 0) return PL_OK;
+    hipLaunchKernelGGL(glrt_batch, dim3((unsigned)grid), dim3(threads), lds, s, r);
+    return launch_ok("batched GLRT kernel");
 }
 
 }  // namespace plk

@@ -37,6 +37,72 @@ PlaneTable contiguous_planes(const pl_c64* stack, int N, int64_t plane);
 // LDS bytes one workgroup may use on the current device.
 size_t max_lds_bytes();
 
+// ---- per-launch arguments of the stage kernels (one per item in batched
+// launches, see batch_device.hpp)
+struct StatsArgs {
+    PlaneTable t;
+    int first, M;
+    int64_t n;  // pixel pairs (16-byte variant) or pixels
+    double* mean;
+    double* var;
+};
+
+struct GlrtArgs {
+    const double* mean;
+    const double* var;
+    Geometry g;
+    int TX, TY, tw, th;
+    double n, thr, rlo, rhi;
+    uint32_t* mask;
+    uint16_t* count;
+    unsigned long long* counters;
+    int64_t gx;  // tiles per tile row
+};
+
+struct CohArgs {
+    PlaneTable t;
+    int N;
+    Geometry g;
+    const uint32_t* mask;
+    float2* coh;
+    float* diag;      // optional [P][N] diagonal of A (SHP-summed |z|^2), or null
+    int TXo;          // output columns per strip
+    int rows_per_wg;  // output rows per workgroup
+    int tile_w;       // staged input columns (even)
+    int pitch;        // records (pixel pairs) per staged row = tile_w / 2
+    int plane;        // records per image plane (wy * pitch, padded)
+    int wave_words;   // 32-bit words of LDS per wavefront
+    int n_pairs;      // pairs per window = (2 hy + 1)(hx + 1)
+    float inv_ppr;    // 1 / (hx + 1), for exact small divisions
+    int vec_rows;     // every image row starts 16-byte aligned (pairs load as 16 bytes)
+    int64_t n_strips; // strips of TXo output columns (batched launches)
+};
+
+struct LinkArgs {
+    const float2* coh;
+    int N;
+    int64_t npix;
+    int ref;
+    int method;
+    float2* ph;
+    float* phase;  // optional [N][npix] angles in (-pi, pi], 0 at the reference
+    float* lam;
+    uint8_t* flags;
+    unsigned long long* counters;
+};
+
+struct CompressArgs {
+    PlaneTable t;
+    int N, first_real;
+    Geometry g;
+    const float2* ph;
+    float2* kappa;
+    int64_t gx;  // blocks per image row
+};
+
+template <typename Args>
+struct BatchRange;
+
 // ---- kernel launchers (each validates nothing; callers check arguments)
 pl_status launch_amp_stats(const PlaneTable& t, int first, int M, int64_t npix, double* mean,
                            double* var, hipStream_t s);
@@ -62,5 +128,35 @@ pl_status launch_vjp_gather(const PlaneTable& t, int N, const Geometry& g, const
                             const float2* S, float2* grad, hipStream_t s);
 pl_status launch_compress(const PlaneTable& t, int N, int first_real, const Geometry& g,
                           const float2* phasors, float2* kappa, hipStream_t s);
+
+// ---- argument set-up and batched (persistent, multi-item) launches
+bool stats_args(const PlaneTable& t, int first, int M, int64_t npix, double* mean, double* var,
+                StatsArgs* a, int64_t* blocks);  // returns whether the 16-byte variant applies
+bool glrt_args(const double* mean, const double* var, const Geometry& g, double n_eff, double alpha,
+               uint32_t* mask, uint16_t* count, unsigned long long* counters, GlrtArgs* a,
+               int64_t* blocks, size_t* lds);  // false when the tile does not fit in LDS
+// tile set-up of one coherence launch: txo_max caps the strip width, rows (> 0)
+// overrides the output rows per workgroup; returns the dynamic LDS bytes
+// (0: does not fit) and the number of workgroups
+size_t coherence_args(CohArgs* a, int nt, bool split, int txo_max, int rows, int64_t* blocks);
+CompressArgs compress_args(const PlaneTable& t, int N, int first_real, const Geometry& g,
+                           const float2* phasors, float2* kappa, int64_t* blocks);
+int64_t link_blocks(int N, int64_t npix);  // workgroups of one linking launch
+
+// kernel entry points of the batched launches (occupancy queries, LDS limits)
+const void* amp_stats_batch_fn(bool vec);
+const void* glrt_batch_fn();
+const void* coherence_batch_fn(int nt, bool split);
+const void* phase_link_batch_fn(int N_class);
+const void* compress_batch_fn();
+pl_status allow_dynamic_lds(const void* fn, size_t lds);
+
+pl_status launch_amp_stats_batch(const BatchRange<StatsArgs>& r, bool vec, int64_t grid, hipStream_t s);
+pl_status launch_shp_select_batch(const BatchRange<GlrtArgs>& r, int threads, size_t lds, int64_t grid,
+                                  hipStream_t s);
+pl_status launch_coherence_batch(const BatchRange<CohArgs>& r, int nt, bool split, size_t lds, int64_t grid,
+                                 hipStream_t s);
+pl_status launch_phase_link_batch(const BatchRange<LinkArgs>& r, int N_class, int64_t grid, hipStream_t s);
+pl_status launch_compress_batch(const BatchRange<CompressArgs>& r, int64_t grid, hipStream_t s);
 
 }  // namespace plk

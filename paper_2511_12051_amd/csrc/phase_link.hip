@@ -24,28 +24,16 @@
 //  4. zeta_i = x_i conj(x_ref), returned as unit phasors.
 #include <cmath>
 
+#include "batch_device.hpp"
 #include "eig_device.hpp"
 
 namespace plk {
 namespace {
 
-struct LinkArgs {
-    const float2* coh;
-    int N;
-    int64_t npix;
-    int ref;
-    int method;
-    float2* ph;
-    float* phase;  // optional [N][npix] angles in (-pi, pi], 0 at the reference
-    float* lam;
-    uint8_t* flags;
-    unsigned long long* counters;
-};
 
 
 template <int NP, int NJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
-void phase_link_kernel(LinkArgs a) {
+__device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     constexpr int GPW = 64 / NP;  // groups (pixels) per wavefront
     // NJ >= N columns are stored and updated per row (N rounded up to a
     // multiple of 4); NP >= N lanes hold the rows.
@@ -70,7 +58,7 @@ void phase_link_kernel(LinkArgs a) {
     float2* xb = reinterpret_cast<float2*>(gbase + 2 * ROW_BYTES);
 
     const int N = a.N;
-    const int64_t pix = ((int64_t)blockIdx.x * (kBlock / 64) + wave) * GPW + grp;
+    const int64_t pix = (block * (kBlock / 64) + wave) * GPW + grp;
     const bool active = pix < a.npix;
     const bool row_live = active && i < N;
 
@@ -181,15 +169,34 @@ void phase_link_kernel(LinkArgs a) {
     }
 }
 
+#define PL_LINK_ATTRS(NP) __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
+
+template <int NP, int NJ>
+__global__ PL_LINK_ATTRS(NP) void phase_link_kernel(LinkArgs a) { link_body<NP, NJ>(a, blockIdx.x); }
+
+template <int NP, int NJ>
+__global__ PL_LINK_ATTRS(NP) void phase_link_batch(BatchRange<LinkArgs> r) {
+    // groups of a block never synchronise with each other, so consecutive
+    // blocks of the stride loop need no barrier
+    for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
+        const int k = batch_item(r.starts, r.n, b);
+        link_body<NP, NJ>(r.items[k], b - r.starts[k]);
+    }
+}
+
 }  // namespace
+
+int64_t link_blocks(int N, int64_t npix) {
+    const int np = N <= 16 ? 16 : 32;
+    const int64_t per_block = (kBlock / 64) * (64 / np);
+    return (npix + per_block - 1) / per_block;
+}
 
 pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int method,
                             float2* phasors, float* phase, float* lambda, uint8_t* flags,
                             unsigned long long* counters, hipStream_t s) {
     LinkArgs a{coh, N, npix, ref, method, phasors, phase, lambda, flags, counters};
-    const int np = N <= 16 ? 16 : 32;
-    const int64_t per_block = (kBlock / 64) * (64 / np);
-    const int64_t blocks = (npix + per_block - 1) / per_block;
+    const int64_t blocks = link_blocks(N, npix);
     if (blocks > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link: too many pixels");
     const dim3 grid((unsigned)blocks), block(kBlock);
     switch ((N + 3) / 4) {  // columns per row: N rounded up to a multiple of 4
@@ -201,6 +208,31 @@ pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int
         default: hipLaunchKernelGGL((phase_link_kernel<32, 32>), grid, block, 0, s, a); break;
     }
     return launch_ok("phase linking kernel");
+}
+
+const void* phase_link_batch_fn(int N_class) {
+    switch (N_class) {
+        case 1: case 2: case 3: return reinterpret_cast<const void*>(phase_link_batch<16, 12>);
+        case 4: return reinterpret_cast<const void*>(phase_link_batch<16, 16>);
+        case 5: return reinterpret_cast<const void*>(phase_link_batch<32, 20>);
+        case 6: return reinterpret_cast<const void*>(phase_link_batch<32, 24>);
+        case 7: return reinterpret_cast<const void*>(phase_link_batch<32, 28>);
+        default: return reinterpret_cast<const void*>(phase_link_batch<32, 32>);
+    }
+}
+
+pl_status launch_phase_link_batch(const BatchRange<LinkArgs>& r, int N_class, int64_t grid, hipStream_t s) {
+    if (r.total == 0) return PL_OK;
+    const dim3 gr((unsigned)grid), block(kBlock);
+    switch (N_class) {  // (N + 3) / 4, shared by every item of the range
+        case 1: case 2: case 3: hipLaunchKernelGGL((phase_link_batch<16, 12>), gr, block, 0, s, r); break;
+        case 4: hipLaunchKernelGGL((phase_link_batch<16, 16>), gr, block, 0, s, r); break;
+        case 5: hipLaunchKernelGGL((phase_link_batch<32, 20>), gr, block, 0, s, r); break;
+        case 6: hipLaunchKernelGGL((phase_link_batch<32, 24>), gr, block, 0, s, r); break;
+        case 7: hipLaunchKernelGGL((phase_link_batch<32, 28>), gr, block, 0, s, r); break;
+        default: hipLaunchKernelGGL((phase_link_batch<32, 32>), gr, block, 0, s, r); break;
+    }
+    return launch_ok("batched phase linking kernel");
 }
 
 }  // namespace plk

@@ -1,6 +1,7 @@
 // Amplitude statistics and their pooled merge (paper Sec. 3.1,
 // eq. merged-mean and eq. merged-variance).  HBM-bound streaming kernels:
 // one thread per two adjacent pixels, 16-byte loads, FP64 accumulation.
+#include "batch_device.hpp"
 #include "internal.hpp"
 
 namespace plk {
@@ -34,35 +35,43 @@ __device__ inline double amp(float re, float im) {
 }
 
 // 16-byte aligned planes with an even pixel count: one float4 = two pixels.
-__global__ __launch_bounds__(kBlock) void amp_stats_vec(PlaneTable t, int first, int M,
-                                                        int64_t npair, double* __restrict__ mean,
-                                                        double* __restrict__ var) {
-    int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (j >= npair) return;
-    Moments a, b;
-    for (int m = 0; m < M; ++m) {
-        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(t.p[first + m]) + j);
-        a.add(amp(v.x, v.y), m);
-        b.add(amp(v.z, v.w), m);
+__device__ __forceinline__ void stats_vec_body(const StatsArgs& a, int64_t block) {
+    int64_t j = block * kBlock + threadIdx.x;
+    if (j >= a.n) return;
+    Moments u, w;
+    for (int m = 0; m < a.M; ++m) {
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a.t.p[a.first + m]) + j);
+        u.add(amp(v.x, v.y), m);
+        w.add(amp(v.z, v.w), m);
     }
     double m0, v0, m1, v1;
-    a.finish(M, &m0, &v0);
-    b.finish(M, &m1, &v1);
-    reinterpret_cast<double2*>(mean)[j] = make_double2(m0, m1);
-    reinterpret_cast<double2*>(var)[j] = make_double2(v0, v1);
+    u.finish(a.M, &m0, &v0);
+    w.finish(a.M, &m1, &v1);
+    reinterpret_cast<double2*>(a.mean)[j] = make_double2(m0, m1);
+    reinterpret_cast<double2*>(a.var)[j] = make_double2(v0, v1);
 }
 
-__global__ __launch_bounds__(kBlock) void amp_stats_scalar(PlaneTable t, int first, int M,
-                                                           int64_t npix, double* __restrict__ mean,
-                                                           double* __restrict__ var) {
-    int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= npix) return;
-    Moments a;
-    for (int m = 0; m < M; ++m) {
-        float2 v = t.p[first + m][p];
-        a.add(amp(v.x, v.y), m);
+__device__ __forceinline__ void stats_scalar_body(const StatsArgs& a, int64_t block) {
+    int64_t p = block * kBlock + threadIdx.x;
+    if (p >= a.n) return;
+    Moments u;
+    for (int m = 0; m < a.M; ++m) {
+        float2 v = a.t.p[a.first + m][p];
+        u.add(amp(v.x, v.y), m);
     }
-    a.finish(M, mean + p, var + p);
+    u.finish(a.M, a.mean + p, a.var + p);
+}
+
+__global__ __launch_bounds__(kBlock) void amp_stats_vec(StatsArgs a) { stats_vec_body(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void amp_stats_scalar(StatsArgs a) { stats_scalar_body(a, blockIdx.x); }
+
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void amp_stats_batch(BatchRange<StatsArgs> r) {
+    for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
+        const int k = batch_item(r.starts, r.n, b);
+        if (VEC) stats_vec_body(r.items[k], b - r.starts[k]);
+        else stats_scalar_body(r.items[k], b - r.starts[k]);
+    }
 }
 
 struct GroupTable {
@@ -92,21 +101,34 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 
 
 }  // namespace
 
-pl_status launch_amp_stats(const PlaneTable& t, int first, int M, int64_t npix, double* mean,
-                           double* var, hipStream_t s) {
+bool stats_args(const PlaneTable& t, int first, int M, int64_t npix, double* mean, double* var,
+                StatsArgs* a, int64_t* blocks) {
     bool vec = (npix % 2 == 0) && aligned16(mean) && aligned16(var);
     for (int m = 0; m < M && vec; ++m) vec = aligned16(t.p[first + m]);
-    if (vec) {
-        int64_t npair = npix / 2;
-        int64_t blocks = (npair + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(amp_stats_vec, dim3((unsigned)blocks), dim3(kBlock), 0, s, t, first, M,
-                           npair, mean, var);
-    } else {
-        int64_t blocks = (npix + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(amp_stats_scalar, dim3((unsigned)blocks), dim3(kBlock), 0, s, t, first,
-                           M, npix, mean, var);
-    }
+    *a = StatsArgs{t, first, M, vec ? npix / 2 : npix, mean, var};
+    *blocks = (a->n + kBlock - 1) / kBlock;
+    return vec;
+}
+
+pl_status launch_amp_stats(const PlaneTable& t, int first, int M, int64_t npix, double* mean,
+                           double* var, hipStream_t s) {
+    StatsArgs a;
+    int64_t blocks;
+    const bool vec = stats_args(t, first, M, npix, mean, var, &a, &blocks);
+    if (vec) hipLaunchKernelGGL(amp_stats_vec, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(amp_stats_scalar, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
     return launch_ok("amplitude statistics kernel");
+}
+
+const void* amp_stats_batch_fn(bool vec) {
+    return vec ? reinterpret_cast<const void*>(amp_stats_batch<true>) : reinterpret_cast<const void*>(amp_stats_batch<false>);
+}
+
+pl_status launch_amp_stats_batch(const BatchRange<StatsArgs>& r, bool vec, int64_t grid, hipStream_t s) {
+    if (r.total == 0) return PL_OK;
+    if (vec) hipLaunchKernelGGL(amp_stats_batch<true>, dim3((unsigned)grid), dim3(kBlock), 0, s, r);
+    else hipLaunchKernelGGL(amp_stats_batch<false>, dim3((unsigned)grid), dim3(kBlock), 0, s, r);
+    return launch_ok("batched amplitude statistics kernel");
 }
 
 pl_status launch_merge_stats(const double* const* means, const double* const* vars,

@@ -1,0 +1,109 @@
+"""Batched, graph-replayed runs over mini-stacks with uneven N (the k-th
+mini-stack of a burst carries k compressed SLCs, so N = 15 + k) against the
+single-call entry points (bit-identical: the same kernel bodies) and, for one
+item, against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import plink_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+WINDOW = (11, 5, 6, 3)
+SPECS = [  # (rows, cols, compressed SLCs): N = 15 + k, every grid ragged against the tiles
+    (96, 390, 0),
+    (150, 300, 2),
+    (99, 384, 5),
+    (120, 258, 7),
+]
+
+
+def _stacks(seed):
+    out = []
+    for i, (R, C, k) in enumerate(SPECS):
+        wl = synth.Workload(f"batch{i}", R, C, 15, k, WINDOW, model="burst")
+        out.append((wl, synth.make_stack(wl, seed=seed + i, device="cuda")))
+    return out
+
+
+def _single(plink, wl, z, prec, stats=None, n_eff=None):
+    mean, var = stats if stats is not None else plink.amplitude_stats(z[wl.n_comp:].contiguous())
+    mask, _ = plink.shp_select(mean, var, n_eff or wl.n_new, wl.window, wl.alpha)
+    coh = plink.estimate_coherence(z, mask, wl.window, precision=prec)
+    ph, _, fl = plink.phase_link(coh, ref=max(0, wl.n_comp - 1))
+    oR, oC = wl.out_shape
+    kap = plink.compress_ministack(z, wl.n_comp, wl.window, ph.view(wl.N, oR, oC))
+    return ph.view(wl.N, oR, oC), fl, kap
+
+
+def _items(stacks, stats1):
+    items = []
+    for i, (wl, z) in enumerate(stacks):
+        it = dict(stack=z, first_real=wl.n_comp, ref=max(0, wl.n_comp - 1))
+        if i == 1:  # supplied (e.g. merged) statistics with their own sample count
+            it.update(mean=stats1[0], var=stats1[1], n_eff=45.0)
+        items.append(it)
+    return items
+
+
+def _check_same(plink, b, stacks, prec, stats1):
+    for i, (wl, z) in enumerate(stacks):
+        ph, fl, kap = _single(plink, wl, z, prec, *( (stats1, 45.0) if i == 1 else (None, None) ))
+        assert torch.equal(b.phasors[i], ph), f"item {i} phasors"
+        assert torch.equal(b.flags[i], fl), f"item {i} flags"
+        assert torch.equal(b.kappa[i], kap), f"item {i} kappa"
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("tune", [False, True])
+def test_batch_matches_single_calls_and_replays(gpu_lib, prec, tune):
+    plink = gpu_lib
+    stacks = _stacks(seed=40)
+    wl1, z1 = stacks[1]
+    stats1 = plink.amplitude_stats(z1[wl1.n_comp:].contiguous())
+    b = plink.Batch(_items(stacks, stats1), WINDOW, precision=prec, autotune=tune)
+    print(b.describe(), flush=True)
+    for rep in range(3):
+        b.run()
+        torch.cuda.synchronize()
+        _check_same(plink, b, stacks, prec, stats1)
+        # refill every input in place with new data; eager work between replays
+        fresh = _stacks(seed=100 + 10 * rep)
+        for (wl, z), (_, znew) in zip(stacks, fresh):
+            z.copy_(znew)
+        s1 = plink.amplitude_stats(z1[wl1.n_comp:].contiguous())
+        stats1[0].copy_(s1[0])
+        stats1[1].copy_(s1[1])
+        torch.cuda.synchronize()
+    assert "graph captured" in b.describe()
+    b.close()
+
+
+def test_batch_item_against_oracle(gpu_lib):
+    plink = gpu_lib
+    stacks = _stacks(seed=60)
+    b = plink.Batch([dict(stack=z, first_real=wl.n_comp, ref=max(0, wl.n_comp - 1)) for wl, z in stacks],
+                    WINDOW, precision="bf16")
+    b.run()
+    torch.cuda.synchronize()
+    wl, z = stacks[1]  # N = 17, two compressed SLCs
+    ref = wl.n_comp - 1
+    r = O.link_ministack(z.cpu().numpy(), wl.n_comp, wl.window, wl.alpha, ref)
+    ph = b.phasors[1].cpu().numpy().reshape(wl.N, -1)
+    err = np.abs(np.angle(ph * np.conj(r["link"]["phasor"])))
+    # well-posed as in the forward parity tests: oracle sensitivity times the
+    # coherence difference present at the pixel (the batch's coherence is the
+    # single-call one bit for bit)
+    mean, var = plink.amplitude_stats(z[wl.n_comp:].contiguous())
+    mask, _ = plink.shp_select(mean, var, wl.n_new, wl.window, wl.alpha)
+    coh = plink.estimate_coherence(z, mask, wl.window, precision="bf16").cpu().numpy()
+    dC = np.abs(coh.astype(np.complex128) - r["coh"]).reshape(coh.shape[0], -1)
+    eps = np.maximum(np.nanmax(np.where(np.isfinite(dC), dC, np.inf), axis=1), 1e-6)
+    sens = O.phase_sensitivity(r["coh"], ref=ref)
+    wp = 3 * sens * eps <= 1e-3
+    print(f"[batch] oracle: {wp.sum()} of {wp.size} well-posed, max err {err[:, wp].max():.2e}", flush=True)
+    assert wp.mean() > 0.9
+    assert err[:, wp].max() <= 1e-3
+    b.close()
