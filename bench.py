@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--only-main", action="store_true",
+                    help="skip the N=25, batched-sequence and adjoint legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -197,6 +199,106 @@ def cpu_baseline(wl_name, seed):
                       f"{wl.window}), {P} output pixels, {wall:.1f} s wall"}
 
 
+def run_path(torch, plink, wl, stack, precs, steps, warmup):
+    """ms/step, per-stage ms and solver counters of the single-call path."""
+    out = {}
+    oR, oC = wl.out_shape
+    P = oR * oC
+    for prec in precs:
+        path = Path(plink, wl, stack, prec)
+        ms = time_steps(torch, path.step, steps, warmup)
+        stages = stage_times(torch, path, max(3, steps // 2))
+        out[prec] = {"ms": ms, "stages": stages, "value": P / (ms * 1e-3)}
+    return out
+
+
+def leg_n25(torch, plink, synth, args):
+    """Mixed precision at scale: 4096x16384, N=25 (10 compressed + 15 new)."""
+    wl = synth.WORKLOADS["scale"]
+    print(f"[bench] generating {wl.name} {wl.N}x{wl.R}x{wl.C}", file=sys.stderr, flush=True)
+    stack = synth.make_stack(wl, seed=args.seed, device="cuda")
+    r = run_path(torch, plink, wl, stack, ["bf16", "fp32"], 3, 1)
+    del stack
+    torch.cuda.empty_cache()
+    return {"workload": f"{wl.R}x{wl.C}, N={wl.N} ({wl.n_comp} compressed + {wl.n_new} new), "
+                        f"half-window {wl.window[0]}x{wl.window[1]}, stride {wl.window[2]}x{wl.window[3]}",
+            "value": r["bf16"]["value"], "unit": "pixels/s", "ms_per_step": r["bf16"]["ms"],
+            "stage_ms": {k: round(v, 4) for k, v in r["bf16"]["stages"].items()},
+            "fp32_value": r["fp32"]["value"], "fp32_ms_per_step": r["fp32"]["ms"],
+            "fp32_stage_ms": {k: round(v, 4) for k, v in r["fp32"]["stages"].items()},
+            "mixed_speedup_vs_fp32": r["fp32"]["ms"] / r["bf16"]["ms"]}
+
+
+def leg_sequence(torch, plink, synth, args, prec):
+    """Sequential batched: 4 bursts of 1024x4096, 8 mini-stacks of 15 SLCs each
+    (N = 15..22), every burst and mini-stack in one graph-replayed plan; the
+    same work pushed through the sequential driver for comparison."""
+    wl = synth.WORKLOADS["sequential"]
+    M, n, Kmax = wl.n_new, wl.ministacks, wl.ministacks - 1
+    oR, oC = wl.out_shape
+    print(f"[bench] generating {wl.bursts} bursts x {n * M} epochs of {wl.R}x{wl.C}", file=sys.stderr, flush=True)
+    seqs = [synth.make_sequence(wl, seed=args.seed, device="cuda", burst=b) for b in range(wl.bursts)]
+    items = []
+    for b, z in enumerate(seqs):
+        st = [plink.amplitude_stats(z[k * M:(k + 1) * M].contiguous()) for k in range(n)]
+        kap = [torch.empty((wl.R, wl.C), dtype=torch.complex64, device="cuda") for _ in range(n)]
+        for k in range(n):
+            K = min(k, Kmax)
+            g = st[k - K:k + 1]
+            mean, var = plink.merge_amplitude_stats(torch.stack([x[0] for x in g]), torch.stack([x[1] for x in g]),
+                                                    [M] * len(g))
+            items.append(dict(planes=kap[k - K:k] + [z[k * M + m] for m in range(M)], first_real=K,
+                              ref=max(0, K - 1), mean=mean, var=var, n_eff=float((K + 1) * M), kappa=kap[k],
+                              level=k))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = plink.Batch(items, wl.window, wl.alpha, precision=prec, autotune=True)
+    plan_s = time.perf_counter() - t0
+    batch.run()  # captures the graph
+    ms = time_steps(torch, batch.run, 3, 1)
+    desc = batch.describe()
+
+    def driver():
+        for z in seqs:
+            s = plink.Sequential(wl.R, wl.C, M, Kmax, wl.window, wl.alpha, precision=prec)
+            for k in range(n):
+                s.push(z[k * M:(k + 1) * M])
+            s.close()
+
+    ms_driver = time_steps(torch, driver, 2, 1)
+    batch.close()
+    px = wl.bursts * n * oR * oC
+    return {"workload": f"{wl.bursts} bursts x {n} mini-stacks of {M} SLCs, {wl.R}x{wl.C}, N=15..22, "
+                        f"half-window {wl.window[0]}x{wl.window[1]}, stride {wl.window[2]}x{wl.window[3]}",
+            "precision": prec, "value": px / (ms * 1e-3), "unit": "pixels/s", "ms_per_run": ms,
+            "output_pixels": px, "driver_ms": ms_driver, "speedup_vs_driver": ms_driver / ms,
+            "plan_and_autotune_s": plan_s,
+            "launches_per_run": int(desc.strip().splitlines()[-1].split()[-1])}
+
+
+def leg_adjoint(torch, plink, synth, args):
+    """Forward (coherence + linking with phases) and adjoint at 512x512, N=20."""
+    wl = synth.WORKLOADS["adjoint"]
+    z = synth.make_stack(wl, seed=args.seed, device="cuda")
+    mean, var = plink.amplitude_stats(z)
+    mask, _ = plink.shp_select(mean, var, wl.n_new, wl.window, wl.alpha)
+    state = {}
+
+    def fwd():
+        coh = plink.estimate_coherence(z, mask, wl.window)
+        state["r"] = plink.phase_link(coh, ref=0, want_phase=True)
+
+    fwd()
+    g = torch.randn((wl.N, wl.R * wl.C), device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    ws = torch.empty((plink.phase_link_vjp_workspace(wl.N, wl.R, wl.C, wl.window),), dtype=torch.uint8,
+                     device="cuda")
+    flags = state["r"][2]
+    ms_f = time_steps(torch, fwd, 5, 1)
+    ms_b = time_steps(torch, lambda: plink.phase_link_vjp(z, mask, flags, wl.window, 0, g, workspace=ws), 5, 1)
+    return {"workload": f"{wl.R}x{wl.C}, N={wl.N}, half-window {wl.window[0]}x{wl.window[1]}, stride 1",
+            "forward_ms": ms_f, "vjp_ms": ms_b, "unit": "ms"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -289,6 +391,10 @@ def main():
                                              if "fp32" in results and "bf16" in results else None)
     line["evd_fraction"] = main_r["evd_frac"]
     line["link_counters"] = main_r["link_counters"]
+    if not args.only_main and args.workload == "burst":
+        line["n25"] = leg_n25(torch, plink, synth, args)
+        line["sequential_batched"] = leg_sequence(torch, plink, synth, args, args.precision)
+        line["adjoint"] = leg_adjoint(torch, plink, synth, args)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a crop (host cores)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.workload, args.seed)

@@ -249,7 +249,11 @@ pl_status pl_seq_load(pl_seq* s, const void* host_buf, size_t bytes, pl_stream s
  * the inputs first) and keeps the fastest.  The first pl_batch_run on a stream
  * captures the launches into a HIP graph; later runs replay it, so every
  * pointer of the plan must stay valid and inputs are refilled in place.
- * Results are identical to the single-call entry points. */
+ * Levels chain mini-stacks: the sequential scheme of Sec. 2.2 over several
+ * bursts is one plan whose level k holds mini-stack k of every burst, its
+ * planes pointing at the kappa outputs of levels < k (statistics merged
+ * beforehand, e.g. with pl_merge_amplitude_stats, since they do not depend on
+ * the linking).  Results are identical to the single-call entry points. */
 typedef struct {
     const pl_c64* stack;  /* [N][R][C]: first_real compressed SLCs, then real images */
     int64_t R, C;
@@ -262,6 +266,10 @@ typedef struct {
     pl_c64* phasors;      /* [N][oR][oC] out */
     uint8_t* flags;       /* [oR*oC] out, or NULL */
     pl_c64* kappa;        /* [R][C] compressed SLC out, or NULL */
+    const pl_c64* const* planes;  /* host array of N device pointers to the
+                                     [R][C] images (used instead of stack), or NULL */
+    int32_t level;        /* items run level by level in increasing order; a
+                             level may read the kappa of lower levels */
 } pl_batch_item;
 
 typedef struct pl_batch pl_batch;

@@ -57,7 +57,8 @@ class _BatchItem(ctypes.Structure):
     _fields_ = [("stack", ctypes.c_void_p), ("R", ctypes.c_int64), ("C", ctypes.c_int64),
                 ("N", ctypes.c_int32), ("first_real", ctypes.c_int32), ("ref_idx", ctypes.c_int32),
                 ("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("n_eff", ctypes.c_double),
-                ("phasors", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("kappa", ctypes.c_void_p)]
+                ("phasors", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
+                ("planes", ctypes.POINTER(ctypes.c_void_p)), ("level", ctypes.c_int32)]
 
 
 _lib = None
@@ -311,13 +312,16 @@ def compress_ministack(stack: torch.Tensor, first_real: int, window, phasors: to
 class Batch:
     """Independent mini-stacks run together: one persistent launch per stage
     and kernel variant, captured into a HIP graph on the first run and
-    replayed afterwards.  Each item is a dict with ``stack`` (complex64
-    [N,R,C], compressed planes first), optional ``first_real`` (0), ``ref``
-    (0), ``mean``/``var`` (float64 [R,C] statistics for the GLRT; computed
-    from the real images when absent), ``n_eff`` and ``kappa`` (True: also
-    produce the compressed SLC).  Inputs must stay where they are: refill the
-    stacks in place between runs.  Outputs: ``phasors[k]`` [N,oR,oC],
-    ``flags[k]`` [oR*oC], ``kappa[k]`` [R,C] or None."""
+    replayed afterwards.  Each item is a dict with either ``stack``
+    (complex64 [N,R,C], compressed planes first) or ``planes`` (a list of N
+    complex64 [R,C] tensors, e.g. compressed SLCs written by lower levels),
+    and optional ``first_real`` (0), ``ref`` (0), ``mean``/``var`` (float64
+    [R,C] statistics for the GLRT; computed from the real images when
+    absent), ``n_eff``, ``level`` (0; levels run in increasing order),
+    ``phasors`` (output tensor [N,oR,oC] to write into) and ``kappa`` (True,
+    False or an output tensor [R,C]).  Inputs must stay where they are:
+    refill them in place between runs.  Outputs: ``phasors[k]``, ``flags[k]``
+    [oR*oC], ``kappa[k]`` (or None)."""
 
     def __init__(self, items, window, alpha=1e-3, precision="fp32", method="emi", autotune=False):
         lib = load()
@@ -325,14 +329,36 @@ class Batch:
         arr = (_BatchItem * len(items))()
         dev = None
         for k, it in enumerate(items):
-            z = it["stack"]
-            _need(z, torch.complex64, 3, "Batch stack")
-            dev = z.device
-            N, R, C = z.shape
+            planes = it.get("planes")
+            if planes is not None:
+                for t in planes:
+                    _need(t, torch.complex64, 2, "Batch plane")
+                N = len(planes)
+                R, C = planes[0].shape
+                dev = planes[0].device
+                z = None
+                parr = (ctypes.c_void_p * N)(*[t.data_ptr() for t in planes])
+                self._keep += list(planes) + [parr]
+            else:
+                z = it["stack"]
+                _need(z, torch.complex64, 3, "Batch stack")
+                N, R, C = z.shape
+                dev = z.device
+                parr = None
             oR, oC = output_grid(R, C, window)
-            ph = torch.empty((N, oR, oC), dtype=torch.complex64, device=z.device)
-            fl = torch.empty((oR * oC,), dtype=torch.uint8, device=z.device)
-            kap = torch.empty((R, C), dtype=torch.complex64, device=z.device) if it.get("kappa", True) else None
+            ph = it.get("phasors")
+            if ph is None:
+                ph = torch.empty((N, oR, oC), dtype=torch.complex64, device=dev)
+            elif ph.dtype != torch.complex64 or ph.numel() != N * oR * oC or not ph.is_contiguous():
+                raise PlinkError("Batch: phasors must be contiguous complex64 [N,oR,oC]")
+            fl = torch.empty((oR * oC,), dtype=torch.uint8, device=dev)
+            kap = it.get("kappa", True)
+            if kap is True:
+                kap = torch.empty((R, C), dtype=torch.complex64, device=dev)
+            elif kap is False:
+                kap = None
+            else:
+                _need(kap, torch.complex64, 2, "Batch kappa")
             mean, var = it.get("mean"), it.get("var")
             for t, nm in ((mean, "mean"), (var, "var")):
                 if t is not None:
@@ -341,10 +367,13 @@ class Batch:
             self.phasors.append(ph)
             self.flags.append(fl)
             self.kappa.append(kap)
-            arr[k] = _BatchItem(z.data_ptr(), R, C, N, int(it.get("first_real", 0)), int(it.get("ref", 0)),
+            arr[k] = _BatchItem(z.data_ptr() if z is not None else None, R, C, N, int(it.get("first_real", 0)),
+                                int(it.get("ref", 0)),
                                 mean.data_ptr() if mean is not None else None,
                                 var.data_ptr() if var is not None else None, float(it.get("n_eff", 0.0)),
-                                ph.data_ptr(), fl.data_ptr(), kap.data_ptr() if kap is not None else None)
+                                ph.data_ptr(), fl.data_ptr(), kap.data_ptr() if kap is not None else None,
+                                ctypes.cast(parr, ctypes.POINTER(ctypes.c_void_p)) if parr is not None else None,
+                                int(it.get("level", 0)))
         self._device = dev
         h = _P()
         _check(lib.pl_batch_plan(arr, len(items), _win(window), float(alpha), _PREC[precision],

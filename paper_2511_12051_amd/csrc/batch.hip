@@ -1,6 +1,7 @@
 // Batched runs of the whole path over independent mini-stacks, one persistent
 // launch per stage and kernel variant, captured once into a HIP graph and
 // replayed (host side; the kernels' batched wrappers live with each stage).
+#include <algorithm>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -66,15 +67,24 @@ void release(Group<Args>& g) {
 
 }  // namespace
 
-struct pl_batch {
-    std::vector<pl_batch_item> items;
-    std::vector<Geometry> geo;
-    std::vector<void*> allocations;
+namespace {
+
+// the launches of one level: one group per stage and kernel variant
+struct Level {
     Group<StatsArgs> stats[2];   // [0] plain loads, [1] 16-byte loads
     Group<GlrtArgs> glrt;
     Group<CohArgs> coh[2];       // [0] 16-row tile, [1] 32-row tile
     Group<LinkArgs> link[9];     // by (N + 3) / 4
     Group<CompressArgs> comp;
+};
+
+}  // namespace
+
+struct pl_batch {
+    std::vector<pl_batch_item> items;
+    std::vector<void*> allocations;
+    std::vector<int> level_ids;  // distinct levels, increasing
+    std::vector<Level> levels;
     bool split = false;
     int cus = 1;
     hipStream_t own = nullptr;   // capture / replay stream (default priority)
@@ -108,8 +118,8 @@ pl_status size_grid(const pl_batch* b, Group<Args>& g, const void* fn) {
     return PL_OK;
 }
 
-pl_status configure_coherence(pl_batch* b, int v, int txo, int rows) {
-    Group<CohArgs>& g = b->coh[v];
+pl_status configure_coherence(pl_batch* b, Level& L, int v, int txo, int rows) {
+    Group<CohArgs>& g = L.coh[v];
     g.starts.assign(1, 0);
     g.lds = 0;
     for (size_t m = 0; m < g.members.size(); ++m) {
@@ -128,27 +138,27 @@ pl_status configure_coherence(pl_batch* b, int v, int txo, int rows) {
     return upload(g);
 }
 
-pl_status enqueue_front(pl_batch* b, hipStream_t s) {  // statistics and GLRT
+pl_status enqueue_front(pl_batch* b, Level& L, hipStream_t s) {  // statistics and GLRT
     for (int v = 0; v < 2; ++v) {
-        if (b->stats[v].empty()) continue;
-        pl_status st = launch_amp_stats_batch(b->stats[v].range(), v == 1, b->stats[v].grid, s);
+        if (L.stats[v].empty()) continue;
+        pl_status st = launch_amp_stats_batch(L.stats[v].range(), v == 1, L.stats[v].grid, s);
         if (st != PL_OK) return st;
     }
-    return launch_shp_select_batch(b->glrt.range(), b->glrt.threads, b->glrt.lds, b->glrt.grid, s);
+    return launch_shp_select_batch(L.glrt.range(), L.glrt.threads, L.glrt.lds, L.glrt.grid, s);
 }
 
-pl_status enqueue_coherence(pl_batch* b, hipStream_t s) {
+pl_status enqueue_coherence(pl_batch* b, Level& L, hipStream_t s) {
     for (int v = 0; v < 2; ++v) {
-        if (b->coh[v].empty()) continue;
-        pl_status st = launch_coherence_batch(b->coh[v].range(), b->coh[v].variant, b->split, b->coh[v].lds,
-                                              b->coh[v].grid, s);
+        if (L.coh[v].empty()) continue;
+        pl_status st = launch_coherence_batch(L.coh[v].range(), L.coh[v].variant, b->split, L.coh[v].lds,
+                                              L.coh[v].grid, s);
         if (st != PL_OK) return st;
     }
     return PL_OK;
 }
 
-pl_status enqueue_link(pl_batch* b, hipStream_t s) {
-    for (auto& g : b->link) {
+pl_status enqueue_link(Level& L, hipStream_t s) {
+    for (auto& g : L.link) {
         if (g.empty()) continue;
         pl_status st = launch_phase_link_batch(g.range(), g.variant, g.grid, s);
         if (st != PL_OK) return st;
@@ -156,12 +166,20 @@ pl_status enqueue_link(pl_batch* b, hipStream_t s) {
     return PL_OK;
 }
 
-pl_status enqueue_all(pl_batch* b, hipStream_t s) {
-    pl_status st = enqueue_front(b, s);
-    if (st == PL_OK) st = enqueue_coherence(b, s);
-    if (st == PL_OK) st = enqueue_link(b, s);
-    if (st == PL_OK && !b->comp.empty()) st = launch_compress_batch(b->comp.range(), b->comp.grid, s);
+pl_status enqueue_level(pl_batch* b, Level& L, hipStream_t s) {
+    pl_status st = enqueue_front(b, L, s);
+    if (st == PL_OK) st = enqueue_coherence(b, L, s);
+    if (st == PL_OK) st = enqueue_link(L, s);
+    if (st == PL_OK && !L.comp.empty()) st = launch_compress_batch(L.comp.range(), L.comp.grid, s);
     return st;
+}
+
+pl_status enqueue_all(pl_batch* b, hipStream_t s) {
+    for (auto& L : b->levels) {
+        pl_status st = enqueue_level(b, L, s);
+        if (st != PL_OK) return st;
+    }
+    return PL_OK;
 }
 
 // average device time of fn over reps launches after one warm-up
@@ -187,60 +205,69 @@ pl_status time_ms(hipStream_t s, F fn, int reps, float* ms) {
     return st;
 }
 
+// Level by level (a level's inputs may be the compressed SLCs of earlier
+// ones): time the candidate coherence tiles and linking grids, keep the
+// fastest, then run the level so that the next one sees its outputs.
 pl_status autotune(pl_batch* b) {
     hipStream_t s = b->own;
-    pl_status st = enqueue_front(b, s);  // SHP masks of the current inputs
-    if (st != PL_OK) return st;
     static const int tiles[][2] = {{16, 0}, {8, 0}, {16, 2}, {16, 8}, {4, 0}};
-    for (int v = 0; v < 2; ++v) {
-        Group<CohArgs>& g = b->coh[v];
-        if (g.empty()) continue;
-        float best = 0.f;
-        int bt = 16, br = 0, bm = 4;
-        for (int mult : {4, 0}) {
-            for (auto& t : tiles) {
+    for (auto& L : b->levels) {
+        pl_status st = enqueue_front(b, L, s);  // SHP masks of the current inputs
+        if (st != PL_OK) return st;
+        for (int v = 0; v < 2; ++v) {
+            Group<CohArgs>& g = L.coh[v];
+            if (g.empty()) continue;
+            float best = 0.f;
+            int bt = 16, br = 0, bm = 4;
+            for (int mult : {4, 0}) {
+                for (auto& t : tiles) {
+                    g.mult = mult;
+                    st = configure_coherence(b, L, v, t[0], t[1]);
+                    if (st != PL_OK) return st;
+                    float ms = 0.f;
+                    st = time_ms(s, [&] { return launch_coherence_batch(g.range(), g.variant, b->split, g.lds, g.grid, s); },
+                                 2, &ms);
+                    if (st != PL_OK) return st;
+                    if (best == 0.f || ms < best) {
+                        best = ms;
+                        bt = t[0];
+                        br = t[1];
+                        bm = mult;
+                    }
+                }
+            }
+            g.mult = bm;
+            st = configure_coherence(b, L, v, bt, br);
+            if (st != PL_OK) return st;
+            g.best_ms = best;
+        }
+        st = enqueue_coherence(b, L, s);  // coherence of the current inputs for the linking runs
+        if (st != PL_OK) return st;
+        for (auto& g : L.link) {
+            if (g.empty()) continue;
+            float best = 0.f;
+            int bm = g.mult;
+            for (int mult : {1, 2, 4, 0}) {
                 g.mult = mult;
-                st = configure_coherence(b, v, t[0], t[1]);
+                st = size_grid(b, g, phase_link_batch_fn(g.variant));
                 if (st != PL_OK) return st;
                 float ms = 0.f;
-                st = time_ms(s, [&] { return launch_coherence_batch(g.range(), g.variant, b->split, g.lds, g.grid, s); },
-                             2, &ms);
+                st = time_ms(s, [&] { return launch_phase_link_batch(g.range(), g.variant, g.grid, s); }, 2, &ms);
                 if (st != PL_OK) return st;
                 if (best == 0.f || ms < best) {
                     best = ms;
-                    bt = t[0];
-                    br = t[1];
                     bm = mult;
                 }
             }
-        }
-        g.mult = bm;
-        st = configure_coherence(b, v, bt, br);
-        if (st != PL_OK) return st;
-        g.best_ms = best;
-    }
-    st = enqueue_coherence(b, s);  // coherence of the current inputs for the linking runs
-    if (st != PL_OK) return st;
-    for (auto& g : b->link) {
-        if (g.empty()) continue;
-        float best = 0.f;
-        int bm = g.mult;
-        for (int mult : {1, 2, 4, 0}) {
-            g.mult = mult;
+            g.mult = bm;
             st = size_grid(b, g, phase_link_batch_fn(g.variant));
             if (st != PL_OK) return st;
-            float ms = 0.f;
-            st = time_ms(s, [&] { return launch_phase_link_batch(g.range(), g.variant, g.grid, s); }, 2, &ms);
-            if (st != PL_OK) return st;
-            if (best == 0.f || ms < best) {
-                best = ms;
-                bm = mult;
-            }
+            g.best_ms = best;
         }
-        g.mult = bm;
-        st = size_grid(b, g, phase_link_batch_fn(g.variant));
-        if (st != PL_OK) return st;
-        g.best_ms = best;
+        if (!L.comp.empty()) {
+            st = launch_compress_batch(L.comp.range(), L.comp.grid, s);
+            if (st != PL_OK) return st;
+        }
     }
     return hip_ok(hipStreamSynchronize(s), "pl_batch_plan: autotune");
 }
@@ -249,11 +276,13 @@ void destroy(pl_batch* b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (auto& g : b->stats) release(g);
-    release(b->glrt);
-    for (auto& g : b->coh) release(g);
-    for (auto& g : b->link) release(g);
-    release(b->comp);
+    for (auto& L : b->levels) {
+        for (auto& g : L.stats) release(g);
+        release(L.glrt);
+        for (auto& g : L.coh) release(g);
+        for (auto& g : L.link) release(g);
+        release(L.comp);
+    }
     for (void* p : b->allocations) (void)hipFree(p);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -283,7 +312,8 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
     for (int k = 0; k < n_items; ++k) {
         const pl_batch_item& it = items[k];
         Geometry g;
-        PL_CHECK(it.stack && it.phasors, PL_ERR_INVALID_ARG, "pl_batch_plan: item %d: NULL stack or phasors", k);
+        PL_CHECK((it.stack || it.planes) && it.phasors, PL_ERR_INVALID_ARG,
+                 "pl_batch_plan: item %d: NULL stack or phasors", k);
         PL_CHECK(it.N >= 1 && it.N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_batch_plan: item %d: N=%d outside 1..%d", k,
                  it.N, kMaxN);
         PL_CHECK(it.first_real >= 0 && it.first_real < it.N, PL_ERR_INVALID_ARG,
@@ -295,6 +325,9 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
         PL_CHECK(make_geometry(it.R, it.C, w, &g) && g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE,
                  "pl_batch_plan: item %d: bad image size or window", k);
         PL_CHECK(g.R <= 2147483647LL, PL_ERR_UNSUPPORTED, "pl_batch_plan: item %d: too many rows", k);
+        if (it.planes)
+            for (int d = 0; d < it.N; ++d)
+                PL_CHECK(it.planes[d], PL_ERR_INVALID_ARG, "pl_batch_plan: item %d: NULL plane %d", k, d);
     }
     pl_batch* b = new pl_batch();
     b->split = prec == PL_PREC_SPLIT_BF16;
@@ -314,11 +347,15 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
         if (st != PL_OK) return bail(st);
     }
     b->items.assign(items, items + n_items);
+    for (int k = 0; k < n_items; ++k) b->level_ids.push_back(items[k].level);
+    std::sort(b->level_ids.begin(), b->level_ids.end());
+    b->level_ids.erase(std::unique(b->level_ids.begin(), b->level_ids.end()), b->level_ids.end());
+    b->levels.resize(b->level_ids.size());
     for (int k = 0; k < n_items; ++k) {
         const pl_batch_item& it = items[k];
+        Level& L = b->levels[std::lower_bound(b->level_ids.begin(), b->level_ids.end(), it.level) - b->level_ids.begin()];
         Geometry g;
         make_geometry(it.R, it.C, w, &g);
-        b->geo.push_back(g);
         const int64_t P = g.oR * g.oC, px = g.R * g.C;
         auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
         const size_t o_mask = 0, o_count = up(o_mask + (size_t)P * g.nw * 4), o_coh = up(o_count + (size_t)P * 2);
@@ -335,14 +372,19 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
         float2* coh = reinterpret_cast<float2*>(base + o_coh);
         const double* mean = it.mean;
         const double* var = it.var;
-        const PlaneTable t = contiguous_planes(it.stack, it.N, px);
+        PlaneTable t{};
+        if (it.planes) {
+            for (int d = 0; d < it.N; ++d) t.p[d] = reinterpret_cast<const float2*>(it.planes[d]);
+        } else {
+            t = contiguous_planes(it.stack, it.N, px);
+        }
         if (!mean) {
             double* m = reinterpret_cast<double*>(base + o_mean);
             double* v = reinterpret_cast<double*>(base + o_var);
             StatsArgs a;
             int64_t blocks;
             const bool vec = stats_args(t, it.first_real, it.N - it.first_real, px, m, v, &a, &blocks);
-            add_member(b->stats[vec ? 1 : 0], k, a, blocks);
+            add_member(L.stats[vec ? 1 : 0], k, a, blocks);
             mean = m;
             var = v;
         }
@@ -353,9 +395,9 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             const double n_eff = it.n_eff > 0 ? it.n_eff : (double)(it.N - it.first_real);
             if (!glrt_args(mean, var, g, n_eff, alpha, mask, count, nullptr, &a, &blocks, &lds))
                 return bail(fail(PL_ERR_UNSUPPORTED, "pl_batch_plan: window/stride too large for the GLRT tile"));
-            add_member(b->glrt, k, a, blocks);
-            b->glrt.threads = a.TX * a.TY;  // same window and stride for every item
-            b->glrt.lds = lds;
+            add_member(L.glrt, k, a, blocks);
+            L.glrt.threads = a.TX * a.TY;  // same window and stride for every item
+            L.glrt.lds = lds;
         }
         {
             CohArgs a{};
@@ -365,14 +407,14 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             a.mask = mask;
             a.coh = coh;
             a.n_pairs = g.wy * (g.hx + 1);
-            Group<CohArgs>& cg = b->coh[it.N <= 16 ? 0 : 1];
+            Group<CohArgs>& cg = L.coh[it.N <= 16 ? 0 : 1];
             cg.variant = it.N <= 16 ? 16 : 32;
             add_member(cg, k, a, 0);  // blocks set by configure_coherence
         }
         {
             LinkArgs a{coh, it.N, P, it.ref_idx, (int)method, reinterpret_cast<float2*>(it.phasors), nullptr,
                        nullptr, it.flags, nullptr};
-            Group<LinkArgs>& lg = b->link[(it.N + 3) / 4];
+            Group<LinkArgs>& lg = L.link[(it.N + 3) / 4];
             lg.variant = (it.N + 3) / 4;
             add_member(lg, k, a, link_blocks(it.N, P));
         }
@@ -380,32 +422,34 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             int64_t blocks;
             const CompressArgs a = compress_args(t, it.N, it.first_real, g, reinterpret_cast<const float2*>(it.phasors),
                                                  reinterpret_cast<float2*>(it.kappa), &blocks);
-            add_member(b->comp, k, a, blocks);
+            add_member(L.comp, k, a, blocks);
         }
     }
-    for (int v = 0; v < 2; ++v) {
-        b->stats[v].threads = 256;
-        if ((st = size_grid(b, b->stats[v], amp_stats_batch_fn(v == 1))) != PL_OK) return bail(st);
-        if ((st = upload(b->stats[v])) != PL_OK) return bail(st);
+    for (auto& L : b->levels) {
+        for (int v = 0; v < 2; ++v) {
+            L.stats[v].threads = 256;
+            if ((st = size_grid(b, L.stats[v], amp_stats_batch_fn(v == 1))) != PL_OK) return bail(st);
+            if ((st = upload(L.stats[v])) != PL_OK) return bail(st);
+        }
+        if ((st = allow_dynamic_lds(glrt_batch_fn(), L.glrt.lds)) != PL_OK) return bail(st);
+        if ((st = size_grid(b, L.glrt, glrt_batch_fn())) != PL_OK) return bail(st);
+        if ((st = upload(L.glrt)) != PL_OK) return bail(st);
+        for (int v = 0; v < 2; ++v) {
+            Group<CohArgs>& g = L.coh[v];
+            if (g.empty()) continue;
+            g.threads = 64 * 8;
+            if ((st = configure_coherence(b, L, v, 16, 0)) != PL_OK) return bail(st);
+        }
+        for (auto& g : L.link) {
+            if (g.empty()) continue;
+            g.threads = 256;
+            if ((st = size_grid(b, g, phase_link_batch_fn(g.variant))) != PL_OK) return bail(st);
+            if ((st = upload(g)) != PL_OK) return bail(st);
+        }
+        L.comp.threads = 256;
+        if ((st = size_grid(b, L.comp, compress_batch_fn())) != PL_OK) return bail(st);
+        if ((st = upload(L.comp)) != PL_OK) return bail(st);
     }
-    if ((st = allow_dynamic_lds(glrt_batch_fn(), b->glrt.lds)) != PL_OK) return bail(st);
-    if ((st = size_grid(b, b->glrt, glrt_batch_fn())) != PL_OK) return bail(st);
-    if ((st = upload(b->glrt)) != PL_OK) return bail(st);
-    for (int v = 0; v < 2; ++v) {
-        Group<CohArgs>& g = b->coh[v];
-        if (g.empty()) continue;
-        g.threads = 64 * 8;
-        if ((st = configure_coherence(b, v, 16, 0)) != PL_OK) return bail(st);
-    }
-    for (auto& g : b->link) {
-        if (g.empty()) continue;
-        g.threads = 256;
-        if ((st = size_grid(b, g, phase_link_batch_fn(g.variant))) != PL_OK) return bail(st);
-        if ((st = upload(g)) != PL_OK) return bail(st);
-    }
-    b->comp.threads = 256;
-    if ((st = size_grid(b, b->comp, compress_batch_fn())) != PL_OK) return bail(st);
-    if ((st = upload(b->comp)) != PL_OK) return bail(st);
     if (tune) {
         // inputs written on the caller's stream are visible to the plan's stream
         st = hip_ok(hipEventRecord(b->ev_in, reinterpret_cast<hipStream_t>(stream)), "pl_batch_plan: event");
@@ -459,41 +503,47 @@ pl_status pl_batch_describe(const pl_batch* b, char* buf, size_t len) {
              b->exec ? "captured" : "not yet");
     s += line;
     int launches = 0;
-    for (int v = 0; v < 2; ++v)
-        if (!b->stats[v].empty()) {
-            ++launches;
-            snprintf(line, sizeof line, "stats%s: %zu items, %lld blocks, grid %lld\n", v ? " (16-byte)" : "",
-                     b->stats[v].members.size(), (long long)b->stats[v].total(), (long long)b->stats[v].grid);
-            s += line;
-        }
-    ++launches;
-    snprintf(line, sizeof line, "glrt: %zu items, %lld blocks, grid %lld\n", b->glrt.members.size(),
-             (long long)b->glrt.total(), (long long)b->glrt.grid);
-    s += line;
-    for (auto& g : b->coh)
-        if (!g.empty()) {
-            ++launches;
-            snprintf(line, sizeof line,
-                     "coherence tile %d%s: %zu items, strip %d, rows %d, %lld blocks, grid %lld, lds %zu, tuned %.3f ms\n",
-                     g.variant, b->split ? " split-bf16" : " fp32", g.members.size(), g.txo, g.args[0].rows_per_wg,
-                     (long long)g.total(), (long long)g.grid, g.lds, g.best_ms);
-            s += line;
-        }
-    for (auto& g : b->link)
-        if (!g.empty()) {
-            ++launches;
-            snprintf(line, sizeof line, "link N<=%d: %zu items, %lld blocks, grid %lld (x%d), tuned %.3f ms\n",
-                     4 * g.variant, g.members.size(), (long long)g.total(), (long long)g.grid, g.mult, g.best_ms);
-            s += line;
-        }
-    if (!b->comp.empty()) {
-        ++launches;
-        snprintf(line, sizeof line, "compress: %zu items, %lld blocks, grid %lld\n", b->comp.members.size(),
-                 (long long)b->comp.total(), (long long)b->comp.grid);
+    for (size_t l = 0; l < b->levels.size(); ++l) {
+        const Level& L = b->levels[l];
+        snprintf(line, sizeof line, "level %d:\n", b->level_ids[l]);
         s += line;
+        for (int v = 0; v < 2; ++v)
+            if (!L.stats[v].empty()) {
+                ++launches;
+                snprintf(line, sizeof line, "  stats%s: %zu items, %lld blocks, grid %lld\n", v ? " (16-byte)" : "",
+                         L.stats[v].members.size(), (long long)L.stats[v].total(), (long long)L.stats[v].grid);
+                s += line;
+            }
+        ++launches;
+        snprintf(line, sizeof line, "  glrt: %zu items, %lld blocks, grid %lld\n", L.glrt.members.size(),
+                 (long long)L.glrt.total(), (long long)L.glrt.grid);
+        s += line;
+        for (auto& g : L.coh)
+            if (!g.empty()) {
+                ++launches;
+                snprintf(line, sizeof line,
+                         "  coherence tile %d%s: %zu items, strip %d, rows %d, %lld blocks, grid %lld, lds %zu, tuned %.3f ms\n",
+                         g.variant, b->split ? " split-bf16" : " fp32", g.members.size(), g.txo, g.args[0].rows_per_wg,
+                         (long long)g.total(), (long long)g.grid, g.lds, g.best_ms);
+                s += line;
+            }
+        for (auto& g : L.link)
+            if (!g.empty()) {
+                ++launches;
+                snprintf(line, sizeof line, "  link N<=%d: %zu items, %lld blocks, grid %lld (x%d), tuned %.3f ms\n",
+                         4 * g.variant, g.members.size(), (long long)g.total(), (long long)g.grid, g.mult, g.best_ms);
+                s += line;
+            }
+        if (!L.comp.empty()) {
+            ++launches;
+            snprintf(line, sizeof line, "  compress: %zu items, %lld blocks, grid %lld\n", L.comp.members.size(),
+                     (long long)L.comp.total(), (long long)L.comp.grid);
+            s += line;
+        }
     }
     snprintf(line, sizeof line, "launches per run %d\n", launches);
     s += line;
+    if (s.size() + 1 > len) s.resize(len - 1);
     snprintf(buf, len, "%s", s.c_str());
     return PL_OK;
 }

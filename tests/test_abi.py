@@ -119,19 +119,24 @@ def test_batch_argument_checks(lib):
     P = ctypes.c_void_p
     fake = 0x1000  # never dereferenced: every call below fails its checks first
     h = P()
-    item = plink._BatchItem(fake, 64, 64, 15, 0, 0, None, None, 0.0, fake, None, None)
+    item = plink._BatchItem(fake, 64, 64, 15, 0, 0, None, None, 0.0, fake, None, None, None, 0)
     items = (plink._BatchItem * 1)(item)
     w = _w(5, 5, 1, 1)
     assert lib.pl_batch_plan(None, 1, w, 1e-3, 0, 0, 0, None, ctypes.byref(h)) == 1
     assert lib.pl_batch_plan(items, 0, w, 1e-3, 0, 0, 0, None, ctypes.byref(h)) == 3
     assert lib.pl_batch_plan(items, 1, w, 1.5, 0, 0, 0, None, ctypes.byref(h)) == 1
     for bad in (dict(N=40), dict(first_real=15), dict(ref_idx=-1), dict(stack=None), dict(R=0)):
-        it = plink._BatchItem(fake, 64, 64, 15, 0, 0, None, None, 0.0, fake, None, None)
+        it = plink._BatchItem(fake, 64, 64, 15, 0, 0, None, None, 0.0, fake, None, None, None, 0)
         for k, v in bad.items():
             setattr(it, k, v)
         arr = (plink._BatchItem * 1)(it)
         assert lib.pl_batch_plan(arr, 1, w, 1e-3, 0, 0, 0, None, ctypes.byref(h)) != 0, bad
-    it = plink._BatchItem(fake, 64, 64, 15, 0, 0, fake, None, 0.0, fake, None, None)  # mean without var
+    it = plink._BatchItem(fake, 64, 64, 15, 0, 0, fake, None, 0.0, fake, None, None, None, 0)  # mean without var
+    assert lib.pl_batch_plan((plink._BatchItem * 1)(it), 1, w, 1e-3, 0, 0, 0, None, ctypes.byref(h)) == 1
+    # a plane list with a NULL plane
+    planes = (ctypes.c_void_p * 15)(*([fake] * 14 + [None]))
+    it = plink._BatchItem(None, 64, 64, 15, 0, 0, None, None, 0.0, fake, None, None,
+                          ctypes.cast(planes, ctypes.POINTER(ctypes.c_void_p)), 0)
     assert lib.pl_batch_plan((plink._BatchItem * 1)(it), 1, w, 1e-3, 0, 0, 0, None, ctypes.byref(h)) == 1
     assert lib.pl_batch_destroy(None) == 0
     assert lib.pl_batch_run(None, None) == 1

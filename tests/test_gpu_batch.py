@@ -107,3 +107,50 @@ def test_batch_item_against_oracle(gpu_lib):
     assert wp.mean() > 0.9
     assert err[:, wp].max() <= 1e-3
     b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_chained_sequence_matches_sequential_driver(gpu_lib, prec):
+    """The sequential scheme of two bursts as one plan: level k holds
+    mini-stack k of both bursts, whose compressed planes are the kappa
+    buffers written by levels < k.  One graph run equals pushing the
+    mini-stacks through the sequential driver, bit for bit."""
+    plink = gpu_lib
+    Kmax, n = 2, 4  # the window of compressed SLCs slides
+    bursts = []
+    for bi in range(2):
+        wl = synth.crop("sequential", 96, 198 if bi == 0 else 252)
+        bursts.append((wl, synth.make_sequence(wl, seed=70 + bi, ministacks=n).cuda()))
+    items, kappas, stats = [], {}, {}
+    for bi, (wl, z) in enumerate(bursts):
+        M = wl.n_new
+        for k in range(n):
+            stats[bi, k] = plink.amplitude_stats(z[k * M:(k + 1) * M].contiguous())
+            kappas[bi, k] = torch.empty((wl.R, wl.C), dtype=torch.complex64, device="cuda")
+    for bi, (wl, z) in enumerate(bursts):
+        M = wl.n_new
+        for k in range(n):
+            K = min(k, Kmax)
+            groups = [stats[bi, j] for j in range(k - K, k + 1)]
+            mean, var = plink.merge_amplitude_stats(torch.stack([g[0] for g in groups]),
+                                                    torch.stack([g[1] for g in groups]), [M] * len(groups))
+            planes = [kappas[bi, j] for j in range(k - K, k)] + [z[k * M + m] for m in range(M)]
+            items.append(dict(planes=planes, first_real=K, ref=max(0, K - 1), mean=mean, var=var,
+                              n_eff=float((K + 1) * M), kappa=kappas[bi, k], level=k))
+    b = plink.Batch(items, bursts[0][0].window, precision=prec, autotune=True)
+    print(b.describe(), flush=True)
+    b.run()
+    torch.cuda.synchronize()
+    it = iter(range(len(items)))
+    for bi, (wl, z) in enumerate(bursts):
+        M = wl.n_new
+        seq = plink.Sequential(wl.R, wl.C, M, Kmax, wl.window, wl.alpha, precision=prec)
+        for k in range(n):
+            i = next(it)
+            ph, kap, fl = seq.push(z[k * M:(k + 1) * M].contiguous(), want_flags=True)
+            K = min(k, Kmax)
+            assert torch.equal(b.phasors[i][K:], ph), f"burst {bi} mini-stack {k} phasors"
+            assert torch.equal(b.flags[i], fl.reshape(-1)), f"burst {bi} mini-stack {k} flags"
+            assert torch.equal(kappas[bi, k], kap), f"burst {bi} mini-stack {k} kappa"
+        seq.close()
+    b.close()
