@@ -311,14 +311,15 @@ __device__ void store_pixel(const CohArgs& a, float* S, const typename Acc<NT>::
     const float dj = diag[j];
     const bool bad = (j < N) && !(dj > 0.f && dj <= 3.4e38f);
     const bool invalid = __ballot(bad) != 0;
-    const float isj = 1.0f / sqrtf(dj);
+    // hardware reciprocal square roots (about 1 ulp), far inside the coherence tolerance
+    const float isj = __builtin_amdgcn_rsqf(dj);
     if (a.diag && lane < NT && j < N) a.diag[pix * N + j] = dj;
     float2* out = a.coh + pix * (int64_t)N * N;
 #pragma unroll
     for (int v = 0; v < Acc<NT>::R; ++v) {
         const int i = Acc<NT>::row(lane, v);
         if (i < N && j < N) {
-            const float isi = 1.0f / sqrtf(diag[i]);
+            const float isi = __builtin_amdgcn_rsqf(diag[i]);
             float2 c = make_float2(re[v] * isi * isj, im[v] * isi * isj);
             if (i == j) c = make_float2(1.f, 0.f);
             if (invalid) c = make_float2(__builtin_nanf(""), __builtin_nanf(""));

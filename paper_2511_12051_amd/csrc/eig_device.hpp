@@ -27,7 +27,7 @@ __device__ __forceinline__ int lane_id() {
 
 // Reductions over the NP lanes of a group.  Within a row of 16 lanes they use
 // DPP lane permutations (quad swaps, half-row and row mirrors), so no LDS
-// round trip is needed; a 32-lane group adds one exchange between rows.
+// round trip is needed; wider groups add exchanges between rows.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
@@ -62,60 +62,84 @@ __device__ __forceinline__ bool gany(bool p, int grp) {
     return (b & m) != 0;
 }
 
+// |z| of an FP32 complex value to about 1e-14 relative, without the FP64
+// square-root sequence: exact sum of squares in FP64, an FP32 reciprocal
+// square root as seed and one Newton step in FP64 (the seed's 2^-23 relative
+// error becomes ~1e-14).
+__device__ __forceinline__ double cabs64(float re, float im) {
+    const double x = fma((double)re, (double)re, (double)im * (double)im);
+    if (!(x > 1e-30) || x > 1e30) return sqrt(x);  // tiny, huge or not finite: the exact path
+    double y = (double)__builtin_amdgcn_rsqf((float)x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return x * y;
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// FP64 counterpart of publish_c without a shift.
+// Gauss-Jordan with deferred row scaling.  Lane i stores its row unscaled,
+// S_i, with a scale sig_i: the true row is sig_i S_i.  At step k the pivot
+// lane publishes S_k with its diagonal slot set to 1, the pivot p and
+// sig_k = 1/p, and keeps them; every other lane i updates
+//   S_i[j] -= (S_i[k] sig_k) S_k[j]  (after setting S_i[k] = 0),
+// which is the in-place Gauss-Jordan step divided through by sig_i.  Nobody
+// rescales a row during the sweep (the pivot lane alone used to, with the
+// rest of the wavefront idle); each lane scales its row once at the end.
+
+// FP64 pivot row: p = g[k] (no shift); sig = 1/p by a hardware reciprocal
+// refined twice by Newton's method.
 template <int NJ>
-__device__ __forceinline__ void publish_d(double (&g)[NJ], int k, double* buf) {
+__device__ __forceinline__ void publish_d(double (&g)[NJ], int k, double* buf, double& sig) {
     const double p = g[k];
-    const double inv = 1.0 / p;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) g[j] *= inv;
-    g[k] = inv;
+    double r = __builtin_amdgcn_rcp(p);
+    r = fma(r, fma(-p, r, 1.0), r);
+    r = fma(r, fma(-p, r, 1.0), r);
+    sig = r;
+    g[k] = 1.0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) buf[j] = g[j];
     buf[NJ] = p;
+    buf[NJ + 1] = r;
 }
 
-// Scales this lane's row k by 1/p, p = m[k] - mu, stores 1/p at k (in-place
-// Gauss-Jordan form) and publishes the row and p for the group.
+// Complex pivot row of (m - mu I): p = m[k] - mu (the shift is applied when a
+// row becomes the pivot; earlier steps only add multiples of pivot rows to
+// it, so this equals shifting first).
 template <int NJ>
-__device__ __forceinline__ void publish_c(float2 (&m)[NJ], int k, float mu, float2* buf) {
+__device__ __forceinline__ void publish_c(float2 (&m)[NJ], int k, float mu, float2* buf, float& sig) {
     const float p = m[k].x - mu;
-    const float inv = 1.0f / p;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) m[j] = make_float2(m[j].x * inv, m[j].y * inv);
-    m[k] = make_float2(inv, 0.f);
+    const float r = __builtin_amdgcn_rcpf(p);
+    sig = r;
+    m[k] = make_float2(1.f, 0.f);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) buf[j] = m[j];
-    buf[NJ] = make_float2(p, 0.f);
+    buf[NJ] = make_float2(p, r);
 }
 
 // In-place complex Gauss-Jordan inversion of the Hermitian matrix (m - mu I),
 // row i of m being this lane's m[].  Lanes with act == false keep m unchanged.
-// Returns (per group) whether every pivot was positive and finite.
-// The shift is subtracted from each diagonal entry when its row becomes the
-// pivot: earlier steps only add multiples of pivot rows to it, so this equals
-// shifting first.  The lane owning row k+1 scales and publishes it right after
-// its step-k update (double-buffered), so each step costs one LDS round trip.
-// All lanes of a group belong to one wavefront and its LDS operations execute
-// in program order, so no barrier is needed between publishing and reading.
+// Returns (per group) whether every pivot was positive and finite, which by
+// Sylvester's law of inertia proves mu below the smallest eigenvalue.
+// The lane owning row k+1 publishes it right after its step-k update
+// (double-buffered), so each step costs one LDS round trip.  All lanes of a
+// group belong to one wavefront and its LDS operations execute in program
+// order, so no barrier is needed between publishing and reading.
 template <int NJ>
 __device__ __forceinline__ bool invert_c(float2 (&m)[NJ], float mu, int N, int i, bool act, float2* rb0, float2* rb1) {
     bool pd = true;
-    if (act && i == 0) publish_c<NJ>(m, 0, mu, rb0);
+    float sig = 1.f;
+    if (act && i == 0) publish_c<NJ>(m, 0, mu, rb0, sig);
 #pragma unroll NJ
     for (int k = 0; k < NJ; ++k) {
         if (k < N) {
             const float2* buf = (k & 1) ? rb1 : rb0;
             float2* nbuf = (k & 1) ? rb0 : rb1;
             if (act) {
-                const float p = buf[NJ].x;
-                pd = pd && (p > 0.f) && (p <= 3.4e38f);
+                const float2 ps = buf[NJ];
+                pd = pd && (ps.x > 0.f) && (ps.x <= 3.4e38f);
                 if (i != k) {
-                    const float2 f = m[k];
+                    const float2 f = make_float2(m[k].x * ps.y, m[k].y * ps.y);
                     m[k] = make_float2(0.f, 0.f);
 #pragma unroll
                     for (int j = 0; j < NJ; ++j) {
@@ -124,9 +148,13 @@ __device__ __forceinline__ bool invert_c(float2 (&m)[NJ], float mu, int N, int i
                         m[j].y = fmaf(-f.x, r.y, fmaf(-f.y, r.x, m[j].y));
                     }
                 }
-                if (k + 1 < N && i == k + 1) publish_c<NJ>(m, (k + 1 < NJ ? k + 1 : NJ - 1), mu, nbuf);
+                if (k + 1 < N && i == k + 1) publish_c<NJ>(m, (k + 1 < NJ ? k + 1 : NJ - 1), mu, nbuf, sig);
             }
         }
+    }
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) m[j] = make_float2(m[j].x * sig, m[j].y * sig);
     }
     return pd;
 }
@@ -160,12 +188,13 @@ __device__ __forceinline__ float2 matvec_lds(const float2* brow, float2 x, int i
 
 // In-place FP64 Gauss-Jordan inversion of G (row i = this lane's g[]) for
 // lanes with act; returns (per group) whether some pivot was <= 1e-6 or not
-// finite, i.e. the inversion failed.  Same publishing scheme as invert_c.
+// finite, i.e. the inversion failed.  Same scheme as invert_c.
 template <int NJ>
 __device__ __forceinline__ bool invert_g(double (&g)[NJ], int N, int i, bool act, double* rbd0, double* rbd1) {
     bool fail = false;
     if (!gany<64>(act, 0)) return false;
-    if (act && i == 0) publish_d<NJ>(g, 0, rbd0);
+    double sig = 1.0;
+    if (act && i == 0) publish_d<NJ>(g, 0, rbd0, sig);
 #pragma unroll NJ
     for (int k = 0; k < NJ; ++k) {
         if (k < N) {
@@ -175,32 +204,36 @@ __device__ __forceinline__ bool invert_g(double (&g)[NJ], int N, int i, bool act
                 const double p = buf[NJ];
                 fail = fail || !(p > kTauPivot && p <= 1.7976931348623157e308);
                 if (i != k) {
-                    const double f = g[k];
+                    const double f = g[k] * buf[NJ + 1];
                     g[k] = 0.0;
 #pragma unroll
                     for (int j = 0; j < NJ; ++j) g[j] = fma(-f, buf[j], g[j]);
                 }
-                if (k + 1 < N && i == k + 1) publish_d<NJ>(g, (k + 1 < NJ ? k + 1 : NJ - 1), nbuf);
+                if (k + 1 < N && i == k + 1) publish_d<NJ>(g, (k + 1 < NJ ? k + 1 : NJ - 1), nbuf, sig);
             }
         }
+    }
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) g[j] *= sig;
     }
     return fail;
 }
 
 // Eigenvector of the smallest eigenvalue of the Hermitian B (this lane's
 // row in LDS at bme[j * kBlock]) by shifted inverse iteration starting from
-// x (unit norm, component ref_lane real and positive).  On return m holds
+// x (unit norm).  On return m holds
 // (B - mu I)^{-1} for the last accepted shift, x the unit eigenvector
 // component of this lane.
 //
-// Every iterate is rotated so that its component at ref_lane (the lane of the
-// reference image in this group) is real and positive.  In FP32 the computed
-// inverse is not exactly Hermitian, so its dominant eigenvalue carries a small
-// phase; without the rotation each step turns the converged vector by that
-// phase and the step length never falls below the tolerance.
+// Every iterate is rotated by the phase of x^H y so that it keeps the phase
+// of the previous one.  In FP32 the computed inverse is not exactly
+// Hermitian, so its dominant eigenvalue carries a small phase; without the
+// rotation each step turns the converged vector by that phase and the step
+// length never falls below the tolerance.
 template <int NP, int NJ>
 __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, float bnorm2, float mu, bool solve,
-                        int N, int i, int ref_lane, float2* rbc0, float2* rbc1, float2* xb, float2& x,
+                        int N, int i, float2* rbc0, float2* rbc1, float2* xb, float2& x,
                         bool& conv, int& it, int& retries) {
     // One factorisation site serves the first shift and its back-off
     // schedule, the refined shifts, and restoring the accepted shift after
@@ -258,18 +291,22 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
         if (!gany<64>(!conv, 0) || it >= kMaxIter) break;
         float2 y = matvec<NJ>(m, x, i, xb);
         const float n2 = gsum<NP>(y.x * y.x + y.y * y.y);
-        const float2 yr = make_float2(__shfl(y.x, ref_lane, 64), __shfl(y.y, ref_lane, 64));
-        const float r2 = yr.x * yr.x + yr.y * yr.y;
-        // scale by conj(y_ref) / (|y_ref| ||y||); plain 1/||y|| if y_ref vanishes
-        const bool gauge = r2 > 1e-30f * n2;
-        const float sc = gauge ? 1.0f / sqrtf(n2 * r2) : 1.0f / sqrtf(n2);
-        const float2 u = gauge ? make_float2(yr.x * sc, -yr.y * sc) : make_float2(sc, 0.f);
+        const float sr = gsum<NP>(x.x * y.x + x.y * y.y);  // s = x^H y
+        const float si = gsum<NP>(x.x * y.y - x.y * y.x);
+        const float s2 = sr * sr + si * si;
+        // scale by conj(s) / (|s| ||y||); plain 1/||y|| if s vanishes
+        const bool gauge = s2 > 1e-30f * n2;
+        // 1 / (||y|| |s|) as a product of two reciprocal square roots (about 1
+        // ulp each), which cannot overflow where n2 * s2 would
+        const float sc = __builtin_amdgcn_rsqf(n2) * (gauge ? __builtin_amdgcn_rsqf(s2) : 1.0f);
+        const float2 u = gauge ? make_float2(sr * sc, -si * sc) : make_float2(sc, 0.f);
         y = cmul(y, u);
         const float dx = y.x - x.x, dy = y.y - x.y;
         const float d2 = gsum<NP>(dx * dx + dy * dy);
         const bool finite = n2 > 0.f && n2 <= 3.4e38f;
-        // contraction rate of the iteration (1 until two steps are known)
-        const float q2 = d2prev > 0.f ? d2 / d2prev : 1.f;
+        // slow contraction: |dx| shrank by less than kRefineRate over the
+        // last step (always true until two steps are known)
+        const bool slow_rate = !(d2prev > 0.f) || d2 > kRefineRate * kRefineRate * d2prev;
         if (!conv) {
             if (finite) x = y;
             if (d2 < kTol2 || !finite) conv = true;
@@ -282,7 +319,7 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
             // from below; while x still mixes several eigenvectors it can lie
             // above lambda_min, so larger margins follow if the inertia check
             // rejects it.
-            const bool slow = !conv && q2 > kRefineRate * kRefineRate;
+            const bool slow = !conv && slow_rate;
             if (gany<64>(slow, 0)) {
                 const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
                 const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);

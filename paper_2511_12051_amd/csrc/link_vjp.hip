@@ -116,8 +116,7 @@ __global__ __launch_bounds__(kBlock) void link_vjp_kernel(VjpArgs a) {
     double gi[NJ];
 #pragma unroll NJ
     for (int j = 0; j < NJ; ++j) {
-        const double re = c[j].x, im = c[j].y;
-        gi[j] = (row_live && j < N) ? sqrt(fma(re, re, im * im)) : 0.0;
+        gi[j] = (row_live && j < N) ? cabs64(c[j].x, c[j].y) : 0.0;
     }
     // an EMI pixel whose |C| no longer inverts cannot be differentiated on the
     // EMI branch: it contributes nothing
@@ -135,8 +134,8 @@ __global__ __launch_bounds__(kBlock) void link_vjp_kernel(VjpArgs a) {
     float2 m[NJ];
     bool conv;
     int it, retries;
-    eig_min<NP, NJ>(m, bme, bnorm2, emi ? 0.99f : evd_shift, !skip, N, i, grp * NP + a.ref, rbc0, rbc1,
-                    xb, x, conv, it, retries);
+    eig_min<NP, NJ>(m, bme, bnorm2, emi ? 0.99f : evd_shift, !skip, N, i, rbc0, rbc1, xb, x, conv, it,
+                    retries);
     const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
     const float lam = gsum<NP>(x.x * bx.x + x.y * bx.y);
 
@@ -187,8 +186,7 @@ __global__ __launch_bounds__(kBlock) void link_vjp_kernel(VjpArgs a) {
     if (emi) {
 #pragma unroll NJ
         for (int j = 0; j < NJ; ++j) {
-            const double re = c[j].x, im = c[j].y;
-            gi[j] = (row_live && j < N) ? sqrt(fma(re, re, im * im)) : 0.0;
+            gi[j] = (row_live && j < N) ? cabs64(c[j].x, c[j].y) : 0.0;
         }
     }
     invert_g<NJ>(gi, N, i, emi && !skip, rbd0, rbd1);

@@ -62,11 +62,31 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     const bool active = pix < a.npix;
     const bool row_live = active && i < N;
 
-    // ---- load row i of C
+    // ---- the wavefront's matrices, consecutive in memory, are read with
+    // coalesced loads into its own columns of brow (element e of the
+    // wavefront at brow[e / 64][64 wave + e % 64]; GPW N^2 <= 64 NJ since
+    // N <= NJ <= NP), then every lane takes its row from there
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const int NN = N * N;
+    float2* stage = &brow[0][wave * 64];
+    {
+        const int64_t pix0 = (block * (kBlock / 64) + wave) * GPW;
+        const int64_t left = a.npix - pix0;
+        const int total = left <= 0 ? 0 : (int)(left < GPW ? left : GPW) * NN;
+        const f32x2* wsrc = reinterpret_cast<const f32x2*>(a.coh) + (left <= 0 ? 0 : pix0 * NN);
+        for (int e = lane, t = 0; e < total; e += 64, ++t) {
+            const f32x2 v = __builtin_nontemporal_load(wsrc + e);
+            stage[t * kBlock + lane] = make_float2(v.x, v.y);
+        }
+    }
+    const int erow = grp * NN + i * N;  // row i of this group's matrix in the staging order
+    auto staged = [&](int j) {
+        const int e = erow + j;
+        return stage[(e >> 6) * kBlock + (e & 63)];
+    };
     float2 c[NJ];
-    const float2* src = a.coh + (active ? pix : 0) * (int64_t)N * N + (int64_t)i * N;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
+    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? staged(j) : make_float2(0.f, 0.f);
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
@@ -83,42 +103,25 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
             x = make_float2(i == a.ref ? 1.f : 0.f, 0.f);
             nrm = 1.f;
         }
-        const float s = 1.0f / sqrtf(nrm);
+        const float s = __builtin_amdgcn_rsqf(nrm);
         x.x *= s;
         x.y *= s;
     }
-    // EVD shift: minus a Gershgorin bound on lambda_max(C), so -C - mu I > 0
-    float evd_shift;
-    {
-        float rs = 0.f;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) rs += sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
-        evd_shift = -(1.0f + 1e-3f) * gmax<NP>(rs) - 1e-3f;
-    }
-
     // ---- 1. FP64 inverse of G = |C|
     bool use_evd = a.method == PL_LINK_EVD;
     double gi[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const double re = c[j].x, im = c[j].y;
-        gi[j] = (row_live && j < N) ? sqrt(fma(re, re, im * im)) : 0.0;
-    }
+    for (int j = 0; j < NJ; ++j) gi[j] = (row_live && j < N) ? cabs64(c[j].x, c[j].y) : 0.0;
     const bool do_emi = !use_evd && !invalid;
     const bool gfail = invert_g<NJ>(gi, N, i, do_emi, rbd0, rbd1);
     use_evd = use_evd || gfail;
 
     // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
-    // of C is read again (an L2 hit) rather than kept live across step 1.
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    // of C is taken from the staging area again rather than kept live across
+    // step 1; every lane reads it before any lane overwrites the area with B
+    // (one wavefront, LDS operations in program order).
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        c[j] = make_float2(0.f, 0.f);
-        if (row_live && j < N) {
-            const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(src) + j);
-            c[j] = make_float2(v.x, v.y);
-        }
-    }
+    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? staged(j) : make_float2(0.f, 0.f);
     float2* bme = &brow[0][threadIdx.x];  // element j at bme[j * kBlock]
     float bnorm2 = 0.f;  // ||row i of B||^2
 #pragma unroll
@@ -129,21 +132,29 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
         bme[j * kBlock] = v;
         bnorm2 += v.x * v.x + v.y * v.y;
     }
-    float mu = use_evd ? evd_shift : 0.99f;
+    float mu = 0.99f;
+    if (use_evd) {
+        // EVD shift: minus a Gershgorin bound on lambda_max(C), so -C - mu I > 0
+        float rs = 0.f;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) rs += __builtin_amdgcn_sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
+        mu = -(1.0f + 1e-3f) * gmax<NP>(rs) - 1e-3f;
+    }
 
     // ---- 3. shifted inverse iteration
     float2 m[NJ];
     bool conv;
     int it, retries;
-    eig_min<NP, NJ>(m, bme, bnorm2, mu, !invalid, N, i, grp * NP + a.ref, rbc0, rbc1, xb, x, conv, it, retries);
+    eig_min<NP, NJ>(m, bme, bnorm2, mu, !invalid, N, i, rbc0, rbc1, xb, x, conv, it, retries);
 
     // ---- 4. eigenvalue, reference and unit phasors
     const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
     const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
     const float2 xr = make_float2(__shfl(x.x, grp * NP + a.ref, 64), __shfl(x.y, grp * NP + a.ref, 64));
     float2 z = make_float2(x.x * xr.x + x.y * xr.y, x.y * xr.x - x.x * xr.y);  // x conj(x_ref)
-    const float zn = sqrtf(z.x * z.x + z.y * z.y);
-    float2 phv = (zn > 0.f && !invalid) ? make_float2(z.x / zn, z.y / zn) : make_float2(1.f, 0.f);
+    const float z2 = z.x * z.x + z.y * z.y;
+    const float zi = __builtin_amdgcn_rsqf(z2);
+    float2 phv = (z2 > 0.f && !invalid) ? make_float2(z.x * zi, z.y * zi) : make_float2(1.f, 0.f);
     if (i == a.ref) phv = make_float2(1.f, 0.f);
     if (row_live) a.ph[(int64_t)i * a.npix + pix] = phv;
     if (row_live && a.phase) a.phase[(int64_t)i * a.npix + pix] = (i == a.ref || invalid) ? 0.f : atan2f(phv.y, phv.x);
@@ -174,8 +185,11 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
 template <int NP, int NJ>
 __global__ PL_LINK_ATTRS(NP) void phase_link_kernel(LinkArgs a) { link_body<NP, NJ>(a, blockIdx.x); }
 
+// the stride loop needs a few registers more than the single launch: allow
+// occupancy 3 for 16-lane groups rather than spilling at 128
 template <int NP, int NJ>
-__global__ PL_LINK_ATTRS(NP) void phase_link_batch(BatchRange<LinkArgs> r) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 3 : 1, NP == 16 ? 4 : 2)))
+void phase_link_batch(BatchRange<LinkArgs> r) {
     // groups of a block never synchronise with each other, so consecutive
     // blocks of the stride loop need no barrier
     for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
