@@ -95,6 +95,14 @@ __global__ __launch_bounds__(kBlock) void link_vjp_kernel(VjpArgs a) {
     for (int j = 0; j < NJ; ++j)
         if (j == a.ref && row_live) x = c[j];
     {
+        // unit-modulus start: the phases of column ref (for consistent phases
+        // the EMI eigenvector has entries of equal modulus)
+        const float x2 = x.x * x.x + x.y * x.y;
+        if (x2 > 0.f) {
+            const float r = __builtin_amdgcn_rsqf(x2);
+            x.x *= r;
+            x.y *= r;
+        }
         float nrm = gsum<NP>(x.x * x.x + x.y * x.y);
         if (!(nrm > 0.f)) {
             x = make_float2(i == a.ref ? 1.f : 0.f, 0.f);

@@ -62,31 +62,13 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     const bool active = pix < a.npix;
     const bool row_live = active && i < N;
 
-    // ---- the wavefront's matrices, consecutive in memory, are read with
-    // coalesced loads into its own columns of brow (element e of the
-    // wavefront at brow[e / 64][64 wave + e % 64]; GPW N^2 <= 64 NJ since
-    // N <= NJ <= NP), then every lane takes its row from there
-    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    // ---- row i of C (each lane reads its own row; a variant staging the
+    // wavefront's matrices through LDS with coalesced loads measured slower)
     const int NN = N * N;
-    float2* stage = &brow[0][wave * 64];
-    {
-        const int64_t pix0 = (block * (kBlock / 64) + wave) * GPW;
-        const int64_t left = a.npix - pix0;
-        const int total = left <= 0 ? 0 : (int)(left < GPW ? left : GPW) * NN;
-        const f32x2* wsrc = reinterpret_cast<const f32x2*>(a.coh) + (left <= 0 ? 0 : pix0 * NN);
-        for (int e = lane, t = 0; e < total; e += 64, ++t) {
-            const f32x2 v = __builtin_nontemporal_load(wsrc + e);
-            stage[t * kBlock + lane] = make_float2(v.x, v.y);
-        }
-    }
-    const int erow = grp * NN + i * N;  // row i of this group's matrix in the staging order
-    auto staged = [&](int j) {
-        const int e = erow + j;
-        return stage[(e >> 6) * kBlock + (e & 63)];
-    };
+    const float2* src = a.coh + (active ? pix : 0) * (int64_t)NN + (int64_t)i * N;
     float2 c[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? staged(j) : make_float2(0.f, 0.f);
+    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
@@ -98,6 +80,14 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     for (int j = 0; j < NJ; ++j)
         if (j == a.ref && row_live) x = c[j];
     {
+        // unit-modulus start: the phases of column ref (for consistent phases
+        // the EMI eigenvector has entries of equal modulus)
+        const float x2 = x.x * x.x + x.y * x.y;
+        if (x2 > 0.f) {
+            const float r = __builtin_amdgcn_rsqf(x2);
+            x.x *= r;
+            x.y *= r;
+        }
         float nrm = gsum<NP>(x.x * x.x + x.y * x.y);
         if (!(nrm > 0.f)) {
             x = make_float2(i == a.ref ? 1.f : 0.f, 0.f);
@@ -117,11 +107,9 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     use_evd = use_evd || gfail;
 
     // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
-    // of C is taken from the staging area again rather than kept live across
-    // step 1; every lane reads it before any lane overwrites the area with B
-    // (one wavefront, LDS operations in program order).
+    // of C is read again (an L2 hit) rather than kept live across step 1.
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? staged(j) : make_float2(0.f, 0.f);
+    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
     float2* bme = &brow[0][threadIdx.x];  // element j at bme[j * kBlock]
     float bnorm2 = 0.f;  // ||row i of B||^2
 #pragma unroll
