@@ -309,7 +309,12 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
         const bool slow_rate = !(d2prev > 0.f) || d2 > kRefineRate * kRefineRate * d2prev;
         if (!conv) {
             if (finite) x = y;
+            // converged: the step is below the tolerance, or the iteration
+            // contracts at rate q < 1/2 and the remaining error, at most
+            // |dx| q / (1 - q) <= 2 |dx| q, is below 2e-6:
+            // d2 < d2prev / 4 and d2 * q^2 = d2^2 / d2prev < (1e-6)^2
             if (d2 < kTol2 || !finite) conv = true;
+            else if (d2prev > 0.f && d2 < 0.25f * d2prev && d2 * d2 < 1e-12f * d2prev) conv = true;
             d2prev = d2;
         }
         ++it;

@@ -168,13 +168,23 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     }
 }
 
-#define PL_LINK_ATTRS(NP) __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
-
+// 32-lane groups (N > 16) run persistently: the grid (a few times the
+// resident workgroups) strides over the pixel blocks, which avoids
+// dispatching hundreds of thousands of short workgroups; 16-lane groups keep
+// one block per workgroup, where the loop would cost the occupancy-4
+// register budget
 template <int NP, int NJ>
-__global__ PL_LINK_ATTRS(NP) void phase_link_kernel(LinkArgs a) { link_body<NP, NJ>(a, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
+void phase_link_kernel(LinkArgs a, int64_t blocks) {
+    if constexpr (NP == 16) {
+        link_body<NP, NJ>(a, blockIdx.x);
+    } else {
+        for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) link_body<NP, NJ>(a, b);
+    }
+}
 
-// the stride loop needs a few registers more than the single launch: allow
-// occupancy 3 for 16-lane groups rather than spilling at 128
+// the stride loop needs a few registers more than 128: allow occupancy 3 for
+// 16-lane groups rather than spilling
 template <int NP, int NJ>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 3 : 1, NP == 16 ? 4 : 2)))
 void phase_link_batch(BatchRange<LinkArgs> r) {
@@ -194,22 +204,43 @@ int64_t link_blocks(int N, int64_t npix) {
     return (npix + per_block - 1) / per_block;
 }
 
+template <int NP, int NJ>
+pl_status launch_persistent(const LinkArgs& a, int64_t blocks, hipStream_t s) {
+    // resident workgroups per CU of this variant, per device (queried once)
+    static int per_cu[64] = {0};
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (!per_cu[dev]) {
+        int n = 0, c = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(phase_link_kernel<NP, NJ>),
+                                                         kBlock, 0) != hipSuccess || n < 1)
+            n = 1;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 1;
+        cus[dev] = c;
+        per_cu[dev] = n;
+    }
+    int64_t grid = NP == 16 ? blocks : (int64_t)per_cu[dev] * cus[dev] * 4;
+    if (grid > blocks) grid = blocks;
+    if (grid > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link: too many pixels");
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((phase_link_kernel<NP, NJ>), dim3((unsigned)grid), dim3(kBlock), 0, s, a, blocks);
+    return launch_ok("phase linking kernel");
+}
+
 pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int method,
                             float2* phasors, float* phase, float* lambda, uint8_t* flags,
                             unsigned long long* counters, hipStream_t s) {
     LinkArgs a{coh, N, npix, ref, method, phasors, phase, lambda, flags, counters};
     const int64_t blocks = link_blocks(N, npix);
-    if (blocks > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link: too many pixels");
-    const dim3 grid((unsigned)blocks), block(kBlock);
     switch ((N + 3) / 4) {  // columns per row: N rounded up to a multiple of 4
-        case 1: case 2: case 3: hipLaunchKernelGGL((phase_link_kernel<16, 12>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((phase_link_kernel<16, 16>), grid, block, 0, s, a); break;
-        case 5: hipLaunchKernelGGL((phase_link_kernel<32, 20>), grid, block, 0, s, a); break;
-        case 6: hipLaunchKernelGGL((phase_link_kernel<32, 24>), grid, block, 0, s, a); break;
-        case 7: hipLaunchKernelGGL((phase_link_kernel<32, 28>), grid, block, 0, s, a); break;
-        default: hipLaunchKernelGGL((phase_link_kernel<32, 32>), grid, block, 0, s, a); break;
+        case 1: case 2: case 3: return launch_persistent<16, 12>(a, blocks, s);
+        case 4: return launch_persistent<16, 16>(a, blocks, s);
+        case 5: return launch_persistent<32, 20>(a, blocks, s);
+        case 6: return launch_persistent<32, 24>(a, blocks, s);
+        case 7: return launch_persistent<32, 28>(a, blocks, s);
+        default: return launch_persistent<32, 32>(a, blocks, s);
     }
-    return launch_ok("phase linking kernel");
 }
 
 const void* phase_link_batch_fn(int N_class) {
