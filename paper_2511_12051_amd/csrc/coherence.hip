@@ -132,13 +132,14 @@ struct RowLoad {
     f32x4 v[kPfRows<NT>][kPfItems];
 };
 
-__device__ __forceinline__ f32x4 fetch_unit(const CohArgs& a, uint32_t dp, int64_t y, int64_t x0) {
+__device__ __forceinline__ f32x4 fetch_unit(const CohArgs& a, const float2* const* planes, uint32_t dp, int64_t y,
+                                           int64_t x0) {
     const Geometry& g = a.g;
     const int d = (int)(dp >> 16), px = (int)(dp & 0xffffu);
     const int64_t x = x0 + 2 * px;
     f32x4 z = {0.f, 0.f, 0.f, 0.f};
     if (y >= 0 && y < g.R) {
-        const float2* row = a.t.p[d] + y * g.C;
+        const float2* row = planes[d] + y * g.C;
         if (a.vec_rows && x >= 0 && x + 1 < g.C) {
             z = *reinterpret_cast<const f32x4*>(row + x);  // 16-byte aligned pair
         } else {
@@ -184,13 +185,13 @@ __device__ __forceinline__ int next_slot(int s, int wy) { return s + 1 == wy ? 0
 
 // Synchronous staging of rows [y_first, y_first + nrows).
 template <bool SPLIT>
-__device__ void load_rows(const CohArgs& a, const Items& it, void* lds, int64_t y_first, int nrows,
-                          int64_t x0) {
+__device__ void load_rows(const CohArgs& a, const float2* const* planes, const Items& it, void* lds,
+                          int64_t y_first, int nrows, int64_t x0) {
     int slot = ring_slot(y_first, a.g.wy);
     for (int r = 0; r < nrows; ++r) {
 #pragma unroll
         for (int k = 0; k < kMaxItems; ++k)
-            if (k < it.n) store_unit<SPLIT>(a, lds, it.dp[k], slot, fetch_unit(a, it.dp[k], y_first + r, x0));
+            if (k < it.n) store_unit<SPLIT>(a, lds, it.dp[k], slot, fetch_unit(a, planes, it.dp[k], y_first + r, x0));
         slot = next_slot(slot, a.g.wy);
     }
 }
@@ -198,18 +199,18 @@ __device__ void load_rows(const CohArgs& a, const Items& it, void* lds, int64_t 
 // Start the global loads of the prefetched units of the next rows; they
 // complete while the current row's pixels are computed.
 template <int NT>
-__device__ __forceinline__ void prefetch_rows(const CohArgs& a, const Items& it, RowLoad<NT>& pf,
-                                              int64_t y_first, int nrows, int64_t x0) {
+__device__ __forceinline__ void prefetch_rows(const CohArgs& a, const float2* const* planes, const Items& it,
+                                              RowLoad<NT>& pf, int64_t y_first, int nrows, int64_t x0) {
 #pragma unroll
     for (int r = 0; r < kPfRows<NT>; ++r)
 #pragma unroll
         for (int k = 0; k < kPfItems; ++k)
-            if (r < nrows && k < it.n) pf.v[r][k] = fetch_unit(a, it.dp[k], y_first + r, x0);
+            if (r < nrows && k < it.n) pf.v[r][k] = fetch_unit(a, planes, it.dp[k], y_first + r, x0);
 }
 
 template <int NT, bool SPLIT>
-__device__ __forceinline__ void commit_rows(const CohArgs& a, const Items& it, void* lds,
-                                            const RowLoad<NT>& pf, int64_t y_first, int nrows,
+__device__ __forceinline__ void commit_rows(const CohArgs& a, const float2* const* planes, const Items& it,
+                                            void* lds, const RowLoad<NT>& pf, int64_t y_first, int nrows,
                                             int64_t x0) {
     const int s0 = ring_slot(y_first, a.g.wy);
     int slot = s0;
@@ -228,7 +229,7 @@ __device__ __forceinline__ void commit_rows(const CohArgs& a, const Items& it, v
 #pragma unroll
         for (int k = 0; k < kMaxItems; ++k)
             if (k < it.n && (k >= kPfItems || r >= kPfRows<NT>))
-                store_unit<SPLIT>(a, lds, it.dp[k], slot, fetch_unit(a, it.dp[k], y_first + r, x0));
+                store_unit<SPLIT>(a, lds, it.dp[k], slot, fetch_unit(a, planes, it.dp[k], y_first + r, x0));
         slot = next_slot(slot, a.g.wy);
     }
 }
@@ -423,7 +424,8 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
 }
 
 template <int NT, bool SPLIT>
-__device__ void coherence_body(const CohArgs& a, int64_t strip, int64_t band, uint32_t* lds_words) {
+__device__ void coherence_body(const CohArgs& a, const float2* const* planes, int64_t strip, int64_t band,
+                               uint32_t* lds_words) {
     const Geometry& g = a.g;
     const int nthreads = blockDim.x;
     const int nwaves = nthreads >> 6;
@@ -447,7 +449,7 @@ __device__ void coherence_body(const CohArgs& a, int64_t strip, int64_t band, ui
     RowLoad<NT> pf;
     const Items items = make_items(a, nthreads);
     // prologue: the full window of the first output row
-    load_rows<SPLIT>(a, items, lds_words, oy0 * g.sy + g.sy / 2 - g.hy, g.wy, x0);
+    load_rows<SPLIT>(a, planes, items, lds_words, oy0 * g.sy + g.sy / 2 - g.hy, g.wy, x0);
     __syncthreads();
     for (int64_t oy = oy0; oy < oy1; ++oy) {
         const int64_t cy = oy * g.sy + g.sy / 2;
@@ -455,7 +457,7 @@ __device__ void coherence_body(const CohArgs& a, int64_t strip, int64_t band, ui
         const int64_t next_first = (cy + g.hy + 1) > (cy + g.sy - g.hy) ? (cy + g.hy + 1) : (cy + g.sy - g.hy);
         const int next_rows = (int)((cy + g.sy + g.hy) - next_first + 1);
         const bool more = oy + 1 < oy1;
-        if (more) prefetch_rows<NT>(a, items, pf, next_first, next_rows, x0);
+        if (more) prefetch_rows<NT>(a, planes, items, pf, next_first, next_rows, x0);
         const int s0 = first_slot(oy);
         int64_t ox = ox0 + wave;
         uint32_t mw = 0;
@@ -471,7 +473,7 @@ __device__ void coherence_body(const CohArgs& a, int64_t strip, int64_t band, ui
         }
         __syncthreads();  // every wave is done with the rows about to be replaced
         if (more) {
-            commit_rows<NT, SPLIT>(a, items, lds_words, pf, next_first, next_rows, x0);
+            commit_rows<NT, SPLIT>(a, planes, items, lds_words, pf, next_first, next_rows, x0);
             __syncthreads();
         }
     }
@@ -480,7 +482,7 @@ __device__ void coherence_body(const CohArgs& a, int64_t strip, int64_t band, ui
 template <int NT, bool SPLIT>
 __global__ __launch_bounds__(64 * kMaxWaves) void coherence_kernel(CohArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
-    coherence_body<NT, SPLIT>(a, blockIdx.x, blockIdx.y, lds_words);
+    coherence_body<NT, SPLIT>(a, a.t.p, blockIdx.x, blockIdx.y, lds_words);
 }
 
 template <int NT, bool SPLIT>
@@ -488,10 +490,13 @@ __global__ __launch_bounds__(64 * kMaxWaves) void coherence_batch(BatchRange<Coh
     extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
     for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
         const int k = batch_item(r.starts, r.n, b);
-        const CohArgs& a = r.items[k];
+        // a local copy of the arguments: the body then keeps them in registers
+        // instead of re-loading them from the table after each store; its
+        // plane pointers are read from the table itself
+        const CohArgs a = r.items[k];
         const int64_t local = b - r.starts[k];
         // the body ends with a workgroup barrier, after which LDS may be refilled
-        coherence_body<NT, SPLIT>(a, local % a.n_strips, local / a.n_strips, lds_words);
+        coherence_body<NT, SPLIT>(a, r.items[k].t.p, local % a.n_strips, local / a.n_strips, lds_words);
     }
 }
 
