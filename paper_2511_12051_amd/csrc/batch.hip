@@ -210,7 +210,7 @@ pl_status time_ms(hipStream_t s, F fn, int reps, float* ms) {
 // fastest, then run the level so that the next one sees its outputs.
 pl_status autotune(pl_batch* b) {
     hipStream_t s = b->own;
-    static const int tiles[][2] = {{16, 0}, {8, 0}, {16, 2}, {16, 8}, {4, 0}};
+    static const int tiles[][2] = {{16, 0}, {12, 0}, {8, 0}, {16, 2}, {12, 8}, {4, 0}};
     for (auto& L : b->levels) {
         pl_status st = enqueue_front(b, L, s);  // SHP masks of the current inputs
         if (st != PL_OK) return st;
@@ -218,7 +218,7 @@ pl_status autotune(pl_batch* b) {
             Group<CohArgs>& g = L.coh[v];
             if (g.empty()) continue;
             float best = 0.f;
-            int bt = 16, br = 0, bm = 4;
+            int bt = coherence_strip(g.variant), br = 0, bm = 4;
             for (int mult : {4, 0}) {
                 for (auto& t : tiles) {
                     g.mult = mult;
@@ -437,8 +437,8 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
         for (int v = 0; v < 2; ++v) {
             Group<CohArgs>& g = L.coh[v];
             if (g.empty()) continue;
-            g.threads = 64 * 8;
-            if ((st = configure_coherence(b, L, v, 16, 0)) != PL_OK) return bail(st);
+            g.threads = coherence_threads(g.variant);
+            if ((st = configure_coherence(b, L, v, coherence_strip(g.variant), 0)) != PL_OK) return bail(st);
         }
         for (auto& g : L.link) {
             if (g.empty()) continue;

@@ -43,10 +43,11 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-#ifndef PL_COH_WAVES
-#define PL_COH_WAVES 8
-#endif
-constexpr int kMaxWaves = PL_COH_WAVES;  // wavefronts per workgroup (one workgroup per CU)
+// wavefronts per workgroup (one workgroup per CU): 12 for 16-row tiles (three
+// per SIMD within the register budget), 8 for 32-row tiles
+template <int NT>
+constexpr int kWaves = NT == 16 ? 12 : 8;
+constexpr int waves_of(int nt) { return nt == 16 ? kWaves<16> : kWaves<32>; }
 
 
 __device__ __forceinline__ void wave_sync() {
@@ -125,7 +126,7 @@ __device__ __forceinline__ Items make_items(const CohArgs& a, int nthreads) {
 // stay in registers); any other unit is staged directly at commit time.
 constexpr int kPfItems = 2;
 template <int NT>
-constexpr int kPfRows = NT == 16 ? 4 : 2;
+constexpr int kPfRows = NT == 16 ? 3 : 2;
 
 template <int NT>
 struct RowLoad {
@@ -480,13 +481,13 @@ __device__ void coherence_body(const CohArgs& a, const float2* const* planes, in
 }
 
 template <int NT, bool SPLIT>
-__global__ __launch_bounds__(64 * kMaxWaves) void coherence_kernel(CohArgs a) {
+__global__ __launch_bounds__(64 * kWaves<NT>) void coherence_kernel(CohArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
     coherence_body<NT, SPLIT>(a, a.t.p, blockIdx.x, blockIdx.y, lds_words);
 }
 
 template <int NT, bool SPLIT>
-__global__ __launch_bounds__(64 * kMaxWaves) void coherence_batch(BatchRange<CohArgs> r) {
+__global__ __launch_bounds__(64 * kWaves<NT>) void coherence_batch(BatchRange<CohArgs> r) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds_words[];
     for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
         const int k = batch_item(r.starts, r.n, b);
@@ -529,7 +530,7 @@ size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req
         const int pitch = tile_w >> 1;
         int plane = g.wy * pitch;
         plane += (1 - plane % 16 + 16) % 16;  // records = 1 mod 16: stride 4 mod 64 words
-        const size_t bytes = (size_t)16 * a.N * plane + (size_t)kMaxWaves * a.wave_words * 4;
+        const size_t bytes = (size_t)16 * a.N * plane + (size_t)waves_of(nt) * a.wave_words * 4;
         if (bytes <= lds_cap) {
             chosen = txo;
             a.tile_w = tile_w;
@@ -542,7 +543,7 @@ size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req
     if (!chosen) return 0;
     a.TXo = chosen;
     a.inv_ppr = 1.0f / (float)(g.hx + 1);
-    if ((int64_t)a.N * (a.tile_w >> 1) > (int64_t)kMaxItems * 64 * kMaxWaves) return 0;
+    if ((int64_t)a.N * (a.tile_w >> 1) > (int64_t)kMaxItems * 64 * waves_of(nt)) return 0;
     a.vec_rows = (g.C % 2) == 0;
     for (int d = 0; d < a.N; ++d)
         if (reinterpret_cast<uintptr_t>(a.t.p[d]) & 15) a.vec_rows = 0;
@@ -571,7 +572,7 @@ pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const 
     const bool split = prec == PL_PREC_SPLIT_BF16;
     const int nt = N <= 16 ? 16 : 32;
     int64_t blocks = 0;
-    const size_t lds = coherence_args(&a, nt, split, 16, 0, &blocks);
+    const size_t lds = coherence_args(&a, nt, split, coherence_strip(nt), 0, &blocks);
     if (!lds) return fail(PL_ERR_UNSUPPORTED, "pl_estimate_coherence: window too large for LDS");
     const int64_t n_bands = blocks / a.n_strips;
     if (a.n_strips > 2147483647LL || n_bands > 65535)
@@ -579,8 +580,8 @@ pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const 
     const void* fn = coherence_fn(nt, split, false);
     pl_status st = allow_dynamic_lds(fn, lds);
     if (st != PL_OK) return st;
-    // always kMaxWaves waves: the staging layout (and its size check) assumes them
-    const int nwaves = kMaxWaves;
+    // always the full wave count: the staging layout (and its size check) assumes it
+    const int nwaves = waves_of(nt);
     if (nt == 16) {
         if (split) hipLaunchKernelGGL((coherence_kernel<16, true>), dim3((unsigned)a.n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
         else hipLaunchKernelGGL((coherence_kernel<16, false>), dim3((unsigned)a.n_strips, (unsigned)n_bands), dim3(64 * nwaves), lds, s, a);
@@ -593,11 +594,14 @@ pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const 
 
 const void* coherence_batch_fn(int nt, bool split) { return coherence_fn(nt, split, true); }
 
+int coherence_threads(int nt) { return 64 * waves_of(nt); }
+int coherence_strip(int nt) { return nt == 16 ? 12 : 16; }  // one output column per wavefront and row
+
 // the caller has raised the kernel's dynamic LDS limit (allow_dynamic_lds)
 pl_status launch_coherence_batch(const BatchRange<CohArgs>& r, int nt, bool split, size_t lds, int64_t grid,
                                  hipStream_t s) {
     if (r.total == 0) return PL_OK;
-    const dim3 gr((unsigned)grid), bl(64 * kMaxWaves);
+    const dim3 gr((unsigned)grid), bl(64 * waves_of(nt));
     if (nt == 16) {
         if (split) hipLaunchKernelGGL((coherence_batch<16, true>), gr, bl, lds, s, r);
         else hipLaunchKernelGGL((coherence_batch<16, false>), gr, bl, lds, s, r);

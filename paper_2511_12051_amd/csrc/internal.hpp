@@ -147,6 +147,8 @@ int64_t link_blocks(int N, int64_t npix);  // workgroups of one linking launch
 const void* amp_stats_batch_fn(bool vec);
 const void* glrt_batch_fn();
 const void* coherence_batch_fn(int nt, bool split);
+int coherence_threads(int nt);  // workgroup size of the coherence kernels
+int coherence_strip(int nt);    // default output columns per strip
 const void* phase_link_batch_fn(int N_class);
 const void* compress_batch_fn();
 pl_status allow_dynamic_lds(const void* fn, size_t lds);
