@@ -159,6 +159,21 @@ def kernel_name(stage, wl, prec):
             "link": f"phase_link_kernel<{tile},{cols}>", "compress": "compress_kernel"}[stage]
 
 
+def source_hash(name):
+    """sha256 prefix of a kernel source file together with the package's
+    device headers (the kernels include them), or None if it is missing."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2511_12051_amd", "csrc")
+    path = os.path.join(csrc, name)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256(open(path, "rb").read())
+    for hdr in sorted(glob.glob(os.path.join(csrc, "*.hpp"))):
+        h.update(open(hdr, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel, wl, prec):
     """HBM bytes per launch of a kernel from the FETCH_SIZE / WRITE_SIZE
     summary under profiles/ (already scaled by the copy calibration), or None
@@ -173,10 +188,7 @@ def measured_traffic(kernel, wl, prec):
             kv = dict(t.split("=", 1) for t in line.split()[1:])
             if kv.get("kernel") != kernel or kv.get("precision") != prec:
                 continue
-            src = os.path.join(ROOT, "paper_2511_12051_amd", "csrc", kv["source"])
-            if not os.path.exists(src):
-                return None
-            if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["sha256"]:
+            if source_hash(kv["source"]) != kv["sha256"]:
                 return None
             return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
     return None
