@@ -186,6 +186,149 @@ __device__ __forceinline__ float2 matvec_lds(const float2* brow, float2 x, int i
     return y;
 }
 
+// ---- 16-lane groups: exchanges by DPP row broadcast.  A group of 16 lanes
+// is one DPP row, and row_newbcast:L hands lane L's register to every lane of
+// the row inside the instruction's operand path.  The pivot row of a
+// Gauss-Jordan step (held by the pivot lane) and the iterate of a mat-vec
+// (one component per lane) then move between lanes without LDS traffic or
+// its round-trip latency.  The arithmetic, and its order, is that of the LDS
+// versions above, so both give identical results.
+template <int L>
+__device__ __forceinline__ float rowcast(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + L, 0xf, 0xf, true));
+}
+template <int L>
+__device__ __forceinline__ double rowcast(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + L, 0xf, 0xf, true);
+}
+
+// Step K onwards of the complex Gauss-Jordan inversion of (m - mu I) with
+// deferred row scaling: every lane reads the pivot p = m_K[K] - mu and forms
+// sig = 1/p itself; the pivot lane keeps its row S_K with the diagonal slot
+// set to 1, every other active lane i subtracts (S_i[K] sig) S_K.
+template <int NJ, int K>
+__device__ __forceinline__ void invert_c16_steps(float2 (&m)[NJ], float mu, int N, int i, bool act,
+                                                 bool& pd, float& sig) {
+    if constexpr (K < NJ) {
+        if (K < N) {
+            const float p = rowcast<K>(m[K].x) - mu;
+            pd = pd && (p > 0.f) && (p <= 3.4e38f);
+            const float r = __builtin_amdgcn_rcpf(p);
+            const bool piv = i == K;
+            sig = piv ? r : sig;
+            const bool upd = act && !piv;
+            const float fx = upd ? m[K].x * r : 0.f;
+            const float fy = upd ? m[K].y * r : 0.f;
+            if (act) m[K] = piv ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const float rx = rowcast<K>(m[j].x), ry = rowcast<K>(m[j].y);
+                m[j].x = fmaf(-fx, rx, fmaf(fy, ry, m[j].x));
+                m[j].y = fmaf(-fx, ry, fmaf(-fy, rx, m[j].y));
+            }
+        }
+        invert_c16_steps<NJ, K + 1>(m, mu, N, i, act, pd, sig);
+    }
+}
+
+template <int NJ>
+__device__ __forceinline__ bool invert_c16(float2 (&m)[NJ], float mu, int N, int i, bool act) {
+    static_assert(NJ <= 16, "one row of 16 lanes per group");
+    bool pd = true;
+    float sig = 1.f;
+    invert_c16_steps<NJ, 0>(m, mu, N, i, act, pd, sig);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) m[j] = make_float2(m[j].x * sig, m[j].y * sig);
+    }
+    return pd;
+}
+
+template <int NJ, int J>
+__device__ __forceinline__ void matvec16_steps(const float2 (&m)[NJ], float2 x, float2& y) {
+    if constexpr (J < NJ) {
+        const float vx = rowcast<J>(x.x), vy = rowcast<J>(x.y);
+        y.x = fmaf(m[J].x, vx, fmaf(-m[J].y, vy, y.x));
+        y.y = fmaf(m[J].x, vy, fmaf(m[J].y, vx, y.y));
+        matvec16_steps<NJ, J + 1>(m, x, y);
+    }
+}
+
+template <int NJ, int J>
+__device__ __forceinline__ void matvec16_lds_steps(const float2* brow, float2 x, float2& y) {
+    if constexpr (J < NJ) {
+        const float2 m = brow[J * kBlock];
+        const float vx = rowcast<J>(x.x), vy = rowcast<J>(x.y);
+        y.x = fmaf(m.x, vx, fmaf(-m.y, vy, y.x));
+        y.y = fmaf(m.x, vy, fmaf(m.y, vx, y.y));
+        matvec16_lds_steps<NJ, J + 1>(brow, x, y);
+    }
+}
+
+template <int NJ, int K>
+__device__ __forceinline__ void invert_g16_steps(double (&g)[NJ], int N, int i, bool act, bool& fail, double& sig) {
+    if constexpr (K < NJ) {
+        if (K < N) {
+            const double p = rowcast<K>(g[K]);
+            fail = fail || (act && !(p > kTauPivot && p <= 1.7976931348623157e308));
+            double r = __builtin_amdgcn_rcp(p);
+            r = fma(r, fma(-p, r, 1.0), r);
+            r = fma(r, fma(-p, r, 1.0), r);
+            const bool piv = i == K;
+            sig = piv ? r : sig;
+            const double f = (act && !piv) ? g[K] * r : 0.0;
+            if (act) g[K] = piv ? 1.0 : 0.0;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) g[j] = fma(-f, rowcast<K>(g[j]), g[j]);
+        }
+        invert_g16_steps<NJ, K + 1>(g, N, i, act, fail, sig);
+    }
+}
+
+template <int NJ>
+__device__ __forceinline__ bool invert_g16(double (&g)[NJ], int N, int i, bool act) {
+    static_assert(NJ <= 16, "one row of 16 lanes per group");
+    if (!gany<64>(act, 0)) return false;
+    bool fail = false;
+    double sig = 1.0;
+    invert_g16_steps<NJ, 0>(g, N, i, act, fail, sig);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) g[j] *= sig;
+    }
+    return fail;
+}
+
+// Dispatch on the group width: DPP row broadcasts for 16 lanes, LDS buffers
+// (rb0, rb1, xb) for 32.
+template <int NP, int NJ>
+__device__ __forceinline__ bool factor_c(float2 (&m)[NJ], float mu, int N, int i, bool act, float2* rb0, float2* rb1) {
+    if constexpr (NP == 16) return invert_c16<NJ>(m, mu, N, i, act);
+    else return invert_c<NJ>(m, mu, N, i, act, rb0, rb1);
+}
+
+template <int NP, int NJ>
+__device__ __forceinline__ float2 group_matvec(const float2 (&m)[NJ], float2 x, int i, float2* xb) {
+    if constexpr (NP == 16) {
+        float2 y = make_float2(0.f, 0.f);
+        matvec16_steps<NJ, 0>(m, x, y);
+        return y;
+    } else {
+        return matvec<NJ>(m, x, i, xb);
+    }
+}
+
+template <int NP, int NJ>
+__device__ __forceinline__ float2 group_matvec_lds(const float2* brow, float2 x, int i, float2* xb) {
+    if constexpr (NP == 16) {
+        float2 y = make_float2(0.f, 0.f);
+        matvec16_lds_steps<NJ, 0>(brow, x, y);
+        return y;
+    } else {
+        return matvec_lds<NJ>(brow, x, i, xb);
+    }
+}
+
 // In-place FP64 Gauss-Jordan inversion of G (row i = this lane's g[]) for
 // lanes with act; returns (per group) whether some pivot was <= 1e-6 or not
 // finite, i.e. the inversion failed.  Same scheme as invert_c.
@@ -218,6 +361,12 @@ __device__ __forceinline__ bool invert_g(double (&g)[NJ], int N, int i, bool act
         for (int j = 0; j < NJ; ++j) g[j] *= sig;
     }
     return fail;
+}
+
+template <int NP, int NJ>
+__device__ __forceinline__ bool factor_g(double (&g)[NJ], int N, int i, bool act, double* rb0, double* rb1) {
+    if constexpr (NP == 16) return invert_g16<NJ>(g, N, i, act);
+    else return invert_g<NJ>(g, N, i, act, rb0, rb1);
 }
 
 // Eigenvector of the smallest eigenvalue of the Hermitian B (this lane's
@@ -253,7 +402,7 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
         if (gany<64>(need, 0)) {
 #pragma unroll NJ
             for (int j = 0; j < NJ; ++j) if (need) m[j] = bme[j * kBlock];
-            const bool ok = invert_c<NJ>(m, mu_req, N, i, need, rbc0, rbc1);
+            const bool ok = factor_c<NP, NJ>(m, mu_req, N, i, need, rbc0, rbc1);
             if (need) {
                 if (ok) {
                     if (stage == 4) d2prev = 0.f;  // the contraction rate changes
@@ -289,7 +438,7 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
             continue;
         }
         if (!gany<64>(!conv, 0) || it >= kMaxIter) break;
-        float2 y = matvec<NJ>(m, x, i, xb);
+        float2 y = group_matvec<NP, NJ>(m, x, i, xb);
         const float n2 = gsum<NP>(y.x * y.x + y.y * y.y);
         const float sr = gsum<NP>(x.x * y.x + x.y * y.y);  // s = x^H y
         const float si = gsum<NP>(x.x * y.y - x.y * y.x);
@@ -326,7 +475,7 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
             // rejects it.
             const bool slow = !conv && slow_rate;
             if (gany<64>(slow, 0)) {
-                const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
+                const float2 bx = group_matvec_lds<NP, NJ>(bme, x, i, xb);
                 const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
                 const float rx = bx.x - rho * x.x, ry = bx.y - rho * x.y;
                 const float res = sqrtf(gsum<NP>(rx * rx + ry * ry));

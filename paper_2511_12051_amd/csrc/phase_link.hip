@@ -103,7 +103,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) gi[j] = (row_live && j < N) ? cabs64(c[j].x, c[j].y) : 0.0;
     const bool do_emi = !use_evd && !invalid;
-    const bool gfail = invert_g<NJ>(gi, N, i, do_emi, rbd0, rbd1);
+    const bool gfail = factor_g<NP, NJ>(gi, N, i, do_emi, rbd0, rbd1);
     use_evd = use_evd || gfail;
 
     // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
@@ -136,7 +136,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     eig_min<NP, NJ>(m, bme, bnorm2, mu, !invalid, N, i, rbc0, rbc1, xb, x, conv, it, retries);
 
     // ---- 4. eigenvalue, reference and unit phasors
-    const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
+    const float2 bx = group_matvec_lds<NP, NJ>(bme, x, i, xb);
     const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
     const float2 xr = make_float2(__shfl(x.x, grp * NP + a.ref, 64), __shfl(x.y, grp * NP + a.ref, 64));
     float2 z = make_float2(x.x * xr.x + x.y * xr.y, x.y * xr.x - x.x * xr.y);  // x conj(x_ref)
