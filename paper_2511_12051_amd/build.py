@@ -38,7 +38,7 @@ def sources():
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++20", "-Wall",
            "-Wno-unused-function", "-I", INCLUDE, "-c", src, "-o", obj] + DEVICE_FLAGS
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -25,6 +25,24 @@ __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
 }
 
+// An opaque copy of a pointer: loads through it are neither merged with
+// earlier loads of the same address nor hoisted above this point (out of a
+// loop), which would keep the loaded values live in registers.
+template <class T>
+__device__ __forceinline__ T* opaque(T* p) {
+    asm volatile("" : "+v"(p));
+    return p;
+}
+__device__ __forceinline__ int opaque_int(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+// the same for a wave-uniform value, kept in a scalar register
+__device__ __forceinline__ int opaque_uniform(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Reductions over the NP lanes of a group.  Within a row of 16 lanes they use
 // DPP lane permutations (quad swaps, half-row and row mirrors), so no LDS
 // round trip is needed; wider groups add exchanges between rows.
@@ -65,13 +83,18 @@ __device__ __forceinline__ bool gany(bool p, int grp) {
 // |z| of an FP32 complex value to about 1e-14 relative, without the FP64
 // square-root sequence: exact sum of squares in FP64, an FP32 reciprocal
 // square root as seed and one Newton step in FP64 (the seed's 2^-23 relative
-// error becomes ~1e-14).
+// error becomes ~1e-14).  Sums of squares outside [1e-30, 1e30] are scaled
+// by an exact power of two into the range of the FP32 seed (every square of
+// an FP32 value lands there after scaling); there is no branch, so the
+// callers' conversions of whole rows stay straight-line code.
 __device__ __forceinline__ double cabs64(float re, float im) {
     const double x = fma((double)re, (double)re, (double)im * (double)im);
-    if (!(x > 1e-30) || x > 1e30) return sqrt(x);  // tiny, huge or not finite: the exact path
-    double y = (double)__builtin_amdgcn_rsqf((float)x);
-    y = y * fma(-0.5 * x * y, y, 1.5);
-    return x * y;
+    const bool tiny = x < 1e-30, huge = x > 1e30;
+    const double xs = x * (tiny ? 0x1p200 : (huge ? 0x1p-200 : 1.0));
+    double y = (double)__builtin_amdgcn_rsqf((float)xs);
+    y = y * fma(-0.5 * xs * y, y, 1.5);
+    const double r = xs * y * (tiny ? 0x1p-100 : (huge ? 0x1p100 : 1.0));
+    return x == 0.0 ? 0.0 : r;
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -186,149 +209,6 @@ __device__ __forceinline__ float2 matvec_lds(const float2* brow, float2 x, int i
     return y;
 }
 
-// ---- 16-lane groups: exchanges by DPP row broadcast.  A group of 16 lanes
-// is one DPP row, and row_newbcast:L hands lane L's register to every lane of
-// the row inside the instruction's operand path.  The pivot row of a
-// Gauss-Jordan step (held by the pivot lane) and the iterate of a mat-vec
-// (one component per lane) then move between lanes without LDS traffic or
-// its round-trip latency.  The arithmetic, and its order, is that of the LDS
-// versions above, so both give identical results.
-template <int L>
-__device__ __forceinline__ float rowcast(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + L, 0xf, 0xf, true));
-}
-template <int L>
-__device__ __forceinline__ double rowcast(double v) {
-    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + L, 0xf, 0xf, true);
-}
-
-// Step K onwards of the complex Gauss-Jordan inversion of (m - mu I) with
-// deferred row scaling: every lane reads the pivot p = m_K[K] - mu and forms
-// sig = 1/p itself; the pivot lane keeps its row S_K with the diagonal slot
-// set to 1, every other active lane i subtracts (S_i[K] sig) S_K.
-template <int NJ, int K>
-__device__ __forceinline__ void invert_c16_steps(float2 (&m)[NJ], float mu, int N, int i, bool act,
-                                                 bool& pd, float& sig) {
-    if constexpr (K < NJ) {
-        if (K < N) {
-            const float p = rowcast<K>(m[K].x) - mu;
-            pd = pd && (p > 0.f) && (p <= 3.4e38f);
-            const float r = __builtin_amdgcn_rcpf(p);
-            const bool piv = i == K;
-            sig = piv ? r : sig;
-            const bool upd = act && !piv;
-            const float fx = upd ? m[K].x * r : 0.f;
-            const float fy = upd ? m[K].y * r : 0.f;
-            if (act) m[K] = piv ? make_float2(1.f, 0.f) : make_float2(0.f, 0.f);
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const float rx = rowcast<K>(m[j].x), ry = rowcast<K>(m[j].y);
-                m[j].x = fmaf(-fx, rx, fmaf(fy, ry, m[j].x));
-                m[j].y = fmaf(-fx, ry, fmaf(-fy, rx, m[j].y));
-            }
-        }
-        invert_c16_steps<NJ, K + 1>(m, mu, N, i, act, pd, sig);
-    }
-}
-
-template <int NJ>
-__device__ __forceinline__ bool invert_c16(float2 (&m)[NJ], float mu, int N, int i, bool act) {
-    static_assert(NJ <= 16, "one row of 16 lanes per group");
-    bool pd = true;
-    float sig = 1.f;
-    invert_c16_steps<NJ, 0>(m, mu, N, i, act, pd, sig);
-    if (act) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) m[j] = make_float2(m[j].x * sig, m[j].y * sig);
-    }
-    return pd;
-}
-
-template <int NJ, int J>
-__device__ __forceinline__ void matvec16_steps(const float2 (&m)[NJ], float2 x, float2& y) {
-    if constexpr (J < NJ) {
-        const float vx = rowcast<J>(x.x), vy = rowcast<J>(x.y);
-        y.x = fmaf(m[J].x, vx, fmaf(-m[J].y, vy, y.x));
-        y.y = fmaf(m[J].x, vy, fmaf(m[J].y, vx, y.y));
-        matvec16_steps<NJ, J + 1>(m, x, y);
-    }
-}
-
-template <int NJ, int J>
-__device__ __forceinline__ void matvec16_lds_steps(const float2* brow, float2 x, float2& y) {
-    if constexpr (J < NJ) {
-        const float2 m = brow[J * kBlock];
-        const float vx = rowcast<J>(x.x), vy = rowcast<J>(x.y);
-        y.x = fmaf(m.x, vx, fmaf(-m.y, vy, y.x));
-        y.y = fmaf(m.x, vy, fmaf(m.y, vx, y.y));
-        matvec16_lds_steps<NJ, J + 1>(brow, x, y);
-    }
-}
-
-template <int NJ, int K>
-__device__ __forceinline__ void invert_g16_steps(double (&g)[NJ], int N, int i, bool act, bool& fail, double& sig) {
-    if constexpr (K < NJ) {
-        if (K < N) {
-            const double p = rowcast<K>(g[K]);
-            fail = fail || (act && !(p > kTauPivot && p <= 1.7976931348623157e308));
-            double r = __builtin_amdgcn_rcp(p);
-            r = fma(r, fma(-p, r, 1.0), r);
-            r = fma(r, fma(-p, r, 1.0), r);
-            const bool piv = i == K;
-            sig = piv ? r : sig;
-            const double f = (act && !piv) ? g[K] * r : 0.0;
-            if (act) g[K] = piv ? 1.0 : 0.0;
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) g[j] = fma(-f, rowcast<K>(g[j]), g[j]);
-        }
-        invert_g16_steps<NJ, K + 1>(g, N, i, act, fail, sig);
-    }
-}
-
-template <int NJ>
-__device__ __forceinline__ bool invert_g16(double (&g)[NJ], int N, int i, bool act) {
-    static_assert(NJ <= 16, "one row of 16 lanes per group");
-    if (!gany<64>(act, 0)) return false;
-    bool fail = false;
-    double sig = 1.0;
-    invert_g16_steps<NJ, 0>(g, N, i, act, fail, sig);
-    if (act) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) g[j] *= sig;
-    }
-    return fail;
-}
-
-// Dispatch on the group width: DPP row broadcasts for 16 lanes, LDS buffers
-// (rb0, rb1, xb) for 32.
-template <int NP, int NJ>
-__device__ __forceinline__ bool factor_c(float2 (&m)[NJ], float mu, int N, int i, bool act, float2* rb0, float2* rb1) {
-    if constexpr (NP == 16) return invert_c16<NJ>(m, mu, N, i, act);
-    else return invert_c<NJ>(m, mu, N, i, act, rb0, rb1);
-}
-
-template <int NP, int NJ>
-__device__ __forceinline__ float2 group_matvec(const float2 (&m)[NJ], float2 x, int i, float2* xb) {
-    if constexpr (NP == 16) {
-        float2 y = make_float2(0.f, 0.f);
-        matvec16_steps<NJ, 0>(m, x, y);
-        return y;
-    } else {
-        return matvec<NJ>(m, x, i, xb);
-    }
-}
-
-template <int NP, int NJ>
-__device__ __forceinline__ float2 group_matvec_lds(const float2* brow, float2 x, int i, float2* xb) {
-    if constexpr (NP == 16) {
-        float2 y = make_float2(0.f, 0.f);
-        matvec16_lds_steps<NJ, 0>(brow, x, y);
-        return y;
-    } else {
-        return matvec_lds<NJ>(brow, x, i, xb);
-    }
-}
-
 // In-place FP64 Gauss-Jordan inversion of G (row i = this lane's g[]) for
 // lanes with act; returns (per group) whether some pivot was <= 1e-6 or not
 // finite, i.e. the inversion failed.  Same scheme as invert_c.
@@ -363,32 +243,361 @@ __device__ __forceinline__ bool invert_g(double (&g)[NJ], int N, int i, bool act
     return fail;
 }
 
-template <int NP, int NJ>
-__device__ __forceinline__ bool factor_g(double (&g)[NJ], int N, int i, bool act, double* rb0, double* rb1) {
-    if constexpr (NP == 16) return invert_g16<NJ>(g, N, i, act);
-    else return invert_g<NJ>(g, N, i, act, rb0, rb1);
+// ---- 16-lane groups: exchanges by DPP row broadcast.  A group of 16 lanes
+// is one DPP row, and row_newbcast:L hands lane L's register to every lane of
+// the row inside the instruction's operand path.  The pivot row of a
+// Gauss-Jordan step (held by its owner lane) and the iterate of a mat-vec
+// (R components per lane) then move between lanes without LDS traffic or its
+// round-trip latency.  Lane l holds the R rows l, l + 16, ... (R = 1 for
+// N <= 16, R = 2 for N <= 32), so row k lives in lane k % 16, slot k / 16.
+// For R = 1 the arithmetic, and its order, is that of the LDS versions above.
+template <int L>
+__device__ __forceinline__ float rowcast(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + L, 0xf, 0xf, true));
+}
+template <int L>
+__device__ __forceinline__ double rowcast(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + L, 0xf, 0xf, true);
 }
 
-// Eigenvector of the smallest eigenvalue of the Hermitian B (this lane's
-// row in LDS at bme[j * kBlock]) by shifted inverse iteration starting from
-// x (unit norm).  On return m holds
-// (B - mu I)^{-1} for the last accepted shift, x the unit eigenvector
-// component of this lane.
+// Step K onwards of the complex Gauss-Jordan inversion of (m - mu I) with
+// deferred row scaling: every lane reads the pivot p = m_K[K] - mu and forms
+// 1/p itself; the owner keeps row K as S_K with the diagonal slot set to 1,
+// every other row i of an active group subtracts (S_i[K] / p) S_K.
+// Step K of the complex Gauss-Jordan inversion of (m - mu I) with deferred
+// row scaling: every lane reads the pivot p = m_K[K] - mu and forms 1/p
+// itself; the owner keeps row K as S_K with the diagonal slot set to 1, every
+// other row i subtracts (S_i[K] / p) S_K.  Every group of the wavefront
+// factors (with its own shift): a per-group "skip" flag would turn the
+// updates into selects that keep two copies of the matrix live.
+template <int R, int NJ, int K>
+__device__ __forceinline__ void invert_cr_step(float2 (&m)[R][NJ], float mu, int l, bool& pd, float (&sig)[R]) {
+    constexpr int KL = K % 16, KS = K / 16;  // owner lane and slot of row K
+    const float p = rowcast<KL>(m[KS][K].x) - mu;
+    pd = pd && (p > 0.f) && (p <= 3.4e38f);
+    const float rp = __builtin_amdgcn_rcpf(p);
+    float fx[R], fy[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool piv = r == KS && l == KL;
+        sig[r] = piv ? rp : sig[r];
+        fx[r] = piv ? 0.f : m[r][K].x * rp;
+        fy[r] = piv ? 0.f : m[r][K].y * rp;
+        m[r][K] = make_float2(piv ? 1.f : 0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const float rx = rowcast<KL>(m[KS][j].x), ry = rowcast<KL>(m[KS][j].y);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            m[r][j].x = fmaf(-fx[r], rx, fmaf(fy[r], ry, m[r][j].x));
+            m[r][j].y = fmaf(-fx[r], ry, fmaf(-fy[r], rx, m[r][j].y));
+        }
+    }
+}
+
+// Smallest N served by the NJ-column kernels (NJ = 12 serves every N up to
+// 12, the wider ones N rounded up to a multiple of 4): steps below it always
+// lie inside N and need no guard (guarding every step splits m's live ranges
+// at each join).
+template <int NJ>
+constexpr int kMinN = NJ <= 12 ? 1 : NJ - 3;
+
+// Steps K onwards; those at or beyond kMinN are guarded by a uniform K < N.
+template <int R, int NJ, int K>
+__device__ __forceinline__ void invert_cr_steps(float2 (&m)[R][NJ], float mu, int N, int l, bool& pd,
+                                                float (&sig)[R]) {
+    if constexpr (K < NJ) {
+        if constexpr (K < kMinN<NJ>) {
+            invert_cr_step<R, NJ, K>(m, mu, l, pd, sig);
+        } else {
+            if (K < N) invert_cr_step<R, NJ, K>(m, mu, l, pd, sig);
+        }
+        invert_cr_steps<R, NJ, K + 1>(m, mu, N, l, pd, sig);
+    }
+}
+
+// In-place inversion of (m - mu I) for every group of the wavefront; returns
+// (per group) whether every pivot was positive and finite (Sylvester's
+// inertia: mu < lambda_min).
+template <int R, int NJ>
+__device__ __forceinline__ bool invert_cr(float2 (&m)[R][NJ], float mu, int N, int l) {
+    static_assert(NJ <= 16 * R, "R rows of 16 lanes per group");
+    bool pd = true;
+    float sig[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sig[r] = 1.f;
+    invert_cr_steps<R, NJ, 0>(m, mu, N, l, pd, sig);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) m[r][j] = make_float2(m[r][j].x * sig[r], m[r][j].y * sig[r]);
+    return pd;
+}
+
+// y += M x over columns J onwards, x_j broadcast from its owner lane
+template <int R, int NJ, int J>
+__device__ __forceinline__ void matvec_r_steps(const float2 (&m)[R][NJ], const float2 (&x)[R], float2 (&y)[R]) {
+    if constexpr (J < NJ) {
+        const float vx = rowcast<J % 16>(x[J / 16].x), vy = rowcast<J % 16>(x[J / 16].y);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            y[r].x = fmaf(m[r][J].x, vx, fmaf(-m[r][J].y, vy, y[r].x));
+            y[r].y = fmaf(m[r][J].x, vy, fmaf(m[r][J].y, vx, y[r].y));
+        }
+        matvec_r_steps<R, NJ, J + 1>(m, x, y);
+    }
+}
+
+// y += B x over columns J onwards, B's row in LDS element-major (one row per lane)
+template <int NJ, int J>
+__device__ __forceinline__ void matvec16_lds_steps(const float2* brow, float2 x, float2& y) {
+    if constexpr (J < NJ) {
+        const float2 m = brow[J * kBlock];
+        const float vx = rowcast<J>(x.x), vy = rowcast<J>(x.y);
+        y.x = fmaf(m.x, vx, fmaf(-m.y, vy, y.x));
+        y.y = fmaf(m.x, vy, fmaf(m.y, vx, y.y));
+        matvec16_lds_steps<NJ, J + 1>(brow, x, y);
+    }
+}
+
+template <int R, int NJ, int K>
+__device__ __forceinline__ void invert_gr_step(double (&g)[R][NJ], int l, bool& fail, double (&sig)[R]) {
+    constexpr int KL = K % 16, KS = K / 16;
+    const double p = rowcast<KL>(g[KS][K]);
+    fail = fail || !(p > kTauPivot && p <= 1.7976931348623157e308);
+    double rp = __builtin_amdgcn_rcp(p);
+    rp = fma(rp, fma(-p, rp, 1.0), rp);
+    rp = fma(rp, fma(-p, rp, 1.0), rp);
+    double f[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool piv = r == KS && l == KL;
+        sig[r] = piv ? rp : sig[r];
+        f[r] = piv ? 0.0 : g[r][K] * rp;
+        g[r][K] = piv ? 1.0 : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const double v = rowcast<KL>(g[KS][j]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) g[r][j] = fma(-f[r], v, g[r][j]);
+    }
+}
+
+template <int R, int NJ, int K>
+__device__ __forceinline__ void invert_gr_steps(double (&g)[R][NJ], int N, int l, bool& fail, double (&sig)[R]) {
+    if constexpr (K < NJ) {
+        if constexpr (K < kMinN<NJ>) {
+            invert_gr_step<R, NJ, K>(g, l, fail, sig);
+        } else {
+            if (K < N) invert_gr_step<R, NJ, K>(g, l, fail, sig);
+        }
+        invert_gr_steps<R, NJ, K + 1>(g, N, l, fail, sig);
+    }
+}
+
+// In-place FP64 inversion of G for every group of the wavefront; returns
+// (per group) whether some pivot was <= 1e-6 or not finite.
+template <int R, int NJ>
+__device__ __forceinline__ bool invert_gr(double (&g)[R][NJ], int N, int l) {
+    static_assert(NJ <= 16 * R, "R rows of 16 lanes per group");
+    bool fail = false;
+    double sig[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sig[r] = 1.0;
+    invert_gr_steps<R, NJ, 0>(g, N, l, fail, sig);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) g[r][j] *= sig[r];
+    return fail;
+}
+
+// ---- Dispatch on the group width: DPP row broadcasts for 16 lanes (R rows
+// per lane), LDS buffers (rb0, rb1, xb) for 32 lanes (one row per lane).
+template <int NP, int R, int NJ>
+__device__ __forceinline__ bool factor_c(float2 (&m)[R][NJ], float mu, int N, int i, bool act, float2* rb0,
+                                         float2* rb1) {
+    if constexpr (NP == 16) return invert_cr<R, NJ>(m, mu, N, i);  // every group factors
+    else return invert_c<NJ>(m[0], mu, N, i, act, rb0, rb1);
+}
+
+template <int NP, int R, int NJ>
+__device__ __forceinline__ void group_matvec(const float2 (&m)[R][NJ], const float2 (&x)[R], float2 (&y)[R], int i,
+                                             float2* xb) {
+    if constexpr (NP == 16) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) y[r] = make_float2(0.f, 0.f);
+        matvec_r_steps<R, NJ, 0>(m, x, y);
+    } else {
+        y[0] = matvec<NJ>(m[0], x[0], i, xb);
+    }
+}
+
+template <int NP, int NJ>
+__device__ __forceinline__ float2 group_matvec_lds(const float2* brow, float2 x, int i, float2* xb) {
+    if constexpr (NP == 16) {
+        float2 y = make_float2(0.f, 0.f);
+        matvec16_lds_steps<NJ, 0>(brow, x, y);
+        return y;
+    } else {
+        return matvec_lds<NJ>(brow, x, i, xb);
+    }
+}
+
+template <int NP, int R, int NJ>
+__device__ __forceinline__ bool factor_g(double (&g)[R][NJ], int N, int i, bool act, double* rb0, double* rb1) {
+    if constexpr (NP == 16) {
+        if (!gany<64>(act, 0)) return false;
+        return invert_gr<R, NJ>(g, N, i) && act;  // every group factors; failures count where act
+    }
+    else return invert_g<NJ>(g[0], N, i, act, rb0, rb1);
+}
+
+// ---- Where the Hermitian B of a group lives between factorisations.
+//
+// BRowLds: each lane's row, element-major over the workgroup (element j of
+// the row at p[j * kBlock]), so the lanes of a wavefront touch consecutive
+// words.  One row per lane.
+template <int NP, int NJ>
+struct BRowLds {
+    float2* p;
+    float2* xb;  // iterate buffer of the group (32-lane groups)
+    int i;
+    // the row is read through an opaque zero offset, so that the loads stay
+    // inside the solver loop (nothing in the loop writes LDS, and hoisted
+    // they would occupy NJ register pairs next to m)
+    __device__ __forceinline__ void load(float2 (&m)[1][NJ], bool pred) const {
+        if (pred) {
+            const float2* q = p + opaque_int(0);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) m[0][j] = q[j * kBlock];
+        }
+    }
+    __device__ __forceinline__ void apply(const float2 (&x)[1], float2 (&y)[1]) const {
+        y[0] = group_matvec_lds<NP, NJ>(p + opaque_int(0), x[0], i, xb);
+    }
+};
+
+// BTriLds: two rows per lane (N <= 32); the upper triangle of each group's
+// matrix (the lower part is its conjugate), so that three wavefronts per
+// SIMD fit in LDS.  Entry (a, b >= a) has index a (2 NJ - a - 1) / 2 + b and
+// the four groups of a wavefront interleave: entry e of group g at
+// w[e * 4 + g].  Index TRI of each group is a write sink for the stores of
+// entries a lane does not own, so that stores need no branch.
+//
+// Offsets: row i's upper entries (i, j >= i) lie at up_i + 4 j, and its
+// lower entries (j < i), read as entry (j, i), at lo_i + 4 cj(j) with
+// cj(j) = j (2 NJ - j - 1) / 2 a compile-time constant, so every access is a
+// per-lane base plus an immediate.  A read loads both candidates and keeps
+// the one on its side of the diagonal; bases are clamped so that both stay
+// inside the buffer.
+template <int NJ>
+struct BTriLds {
+    static constexpr int TRI = NJ * (NJ + 1) / 2;
+    static constexpr int GPW = 4;
+    static constexpr int WAVE_ENTRIES = (TRI + 1) * GPW;  // float2 per wavefront
+    static constexpr int cj(int j) { return j * (2 * NJ - j - 1) / 2; }
+    float2* w;  // this wavefront's buffer
+    int g, l, N;
+
+    __device__ __forceinline__ int up_base(int ll, int r) const {
+        const int i = ll + 16 * r;
+        return (i * (2 * NJ - i - 1) / 2) * GPW + g;
+    }
+    __device__ __forceinline__ int lo_base(int ll, int r) const {
+        const int i = min(ll + 16 * r, NJ - 1);
+        return i * GPW + g;
+    }
+    __device__ __forceinline__ int sink() const { return TRI * GPW + g; }
+
+    // B[ll + 16 r][J]; zero outside n x n.  The entry's offset is selected
+    // first and read with one load (selecting between two loaded values
+    // lets the compiler put each load in a branch of its own, with a wait).
+    template <int J>
+    __device__ __forceinline__ float2 get(int ub, int lb, int ll, int r, int n) const {
+        const int i = ll + 16 * r;
+        const bool up = J >= i;
+        const int o = up ? ub + J * GPW : lb + cj(J) * GPW;  // entry (i, J), or (J, i) below the diagonal
+        const float2 v = w[o];
+        const float2 h = make_float2(v.x, up ? v.y : -v.y);
+        return (i < n && J < n) ? h : make_float2(0.f, 0.f);
+    }
+    // offset of entry (i, J) if this lane owns it (J >= i, both < N), else the sink
+    template <int J>
+    __device__ __forceinline__ int own(int ub, int ll, int r, int n) const {
+        const int i = ll + 16 * r;
+        return (J >= i && i < n && J < n) ? ub + J * GPW : sink();
+    }
+
+    template <int J>
+    __device__ __forceinline__ void load_steps(float2 (&m)[2][NJ], const int (&ub)[2], const int (&lb)[2], int ll,
+                                               int n) const {
+        if constexpr (J < NJ) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r) m[r][J] = get<J>(ub[r], lb[r], ll, r, n);
+            load_steps<J + 1>(m, ub, lb, ll, n);
+        }
+    }
+    // one branch around the whole reload: the loads of the lanes with pred
+    // write m in place (a select per entry would keep both copies live).
+    // The lane index and N are taken through opaque copies so that the
+    // offsets are formed here rather than kept live across the solver loop.
+    __device__ __forceinline__ void load(float2 (&m)[2][NJ], bool pred) const {
+        if (pred) {
+            const int ll = opaque_int(l), n = opaque_uniform(N);
+            const int ub[2] = {up_base(ll, 0), up_base(ll, 1)}, lb[2] = {lo_base(ll, 0), lo_base(ll, 1)};
+            load_steps<0>(m, ub, lb, ll, n);
+        }
+    }
+    template <int J>
+    __device__ __forceinline__ void apply_steps(const int (&ub)[2], const int (&lb)[2], int ll, int n,
+                                                const float2 (&x)[2], float2 (&y)[2]) const {
+        if constexpr (J < NJ) {
+            const float vx = rowcast<J % 16>(x[J / 16].x), vy = rowcast<J % 16>(x[J / 16].y);
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const float2 b = get<J>(ub[r], lb[r], ll, r, n);
+                y[r].x = fmaf(b.x, vx, fmaf(-b.y, vy, y[r].x));
+                y[r].y = fmaf(b.x, vy, fmaf(b.y, vx, y[r].y));
+            }
+            // at most four columns of loads in flight: issued all at once they
+            // would need 8 NJ registers next to the factorisation in m
+            if constexpr (J % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+            apply_steps<J + 1>(ub, lb, ll, n, x, y);
+        }
+    }
+    // y = B x for this lane's two rows
+    __device__ __forceinline__ void apply(const float2 (&x)[2], float2 (&y)[2]) const {
+        const int ll = opaque_int(l), n = opaque_uniform(N);
+        const int ub[2] = {up_base(ll, 0), up_base(ll, 1)}, lb[2] = {lo_base(ll, 0), lo_base(ll, 1)};
+        y[0] = y[1] = make_float2(0.f, 0.f);
+        apply_steps<0>(ub, lb, ll, n, x, y);
+    }
+};
+
+// Eigenvector of the smallest eigenvalue of the Hermitian B (rows held as
+// the view bv describes) by shifted inverse iteration starting from x (unit
+// norm; R components per lane).  On return m holds (B - mu I)^{-1} for the
+// last accepted shift and x the unit eigenvector components of this lane.
 //
 // Every iterate is rotated by the phase of x^H y so that it keeps the phase
 // of the previous one.  In FP32 the computed inverse is not exactly
 // Hermitian, so its dominant eigenvalue carries a small phase; without the
 // rotation each step turns the converged vector by that phase and the step
 // length never falls below the tolerance.
-template <int NP, int NJ>
-__device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, float bnorm2, float mu, bool solve,
-                        int N, int i, float2* rbc0, float2* rbc1, float2* xb, float2& x,
-                        bool& conv, int& it, int& retries) {
+template <int NP, int R, int NJ, class BV>
+__device__ __forceinline__ void eig_min_r(float2 (&m)[R][NJ], const BV& bv, float bnorm2, float mu, bool solve,
+                                          int N, int i, float2* rbc0, float2* rbc1, float2* xb, float2 (&x)[R],
+                                          bool& conv, int& it, int& retries) {
     // One factorisation site serves the first shift and its back-off
     // schedule, the refined shifts, and restoring the accepted shift after
     // every refined candidate was rejected.
-#pragma unroll NJ
-    for (int j = 0; j < NJ; ++j) m[j] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) m[r][j] = make_float2(0.f, 0.f);
     float mu_req = mu;    // shift of the pending factorisation
     bool need = solve;    // this group waits for a factorisation
     int stage = 0;        // 0..3: first-shift schedule, 4: refining, 5: restoring
@@ -400,9 +609,12 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
     float d2prev = 0.f;
     for (int guard = 0; guard < 2 * kMaxIter; ++guard) {
         if (gany<64>(need, 0)) {
-#pragma unroll NJ
-            for (int j = 0; j < NJ; ++j) if (need) m[j] = bme[j * kBlock];
-            const bool ok = factor_c<NP, NJ>(m, mu_req, N, i, need, rbc0, rbc1);
+            // 16-lane groups: every group of the wavefront factors; those
+            // without a pending request redo their accepted shift, which
+            // reproduces their inverse exactly
+            if constexpr (NP == 16) bv.load(m, true);
+            else bv.load(m, need);
+            const bool ok = factor_c<NP, R, NJ>(m, need ? mu_req : mu, N, i, need, rbc0, rbc1);
             if (need) {
                 if (ok) {
                     if (stage == 4) d2prev = 0.f;  // the contraction rate changes
@@ -438,10 +650,18 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
             continue;
         }
         if (!gany<64>(!conv, 0) || it >= kMaxIter) break;
-        float2 y = group_matvec<NP, NJ>(m, x, i, xb);
-        const float n2 = gsum<NP>(y.x * y.x + y.y * y.y);
-        const float sr = gsum<NP>(x.x * y.x + x.y * y.y);  // s = x^H y
-        const float si = gsum<NP>(x.x * y.y - x.y * y.x);
+        float2 y[R];
+        group_matvec<NP, R, NJ>(m, x, y, i, xb);
+        float n2 = 0.f, sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            n2 += y[r].x * y[r].x + y[r].y * y[r].y;
+            sr += x[r].x * y[r].x + x[r].y * y[r].y;  // s = x^H y
+            si += x[r].x * y[r].y - x[r].y * y[r].x;
+        }
+        n2 = gsum<NP>(n2);
+        sr = gsum<NP>(sr);
+        si = gsum<NP>(si);
         const float s2 = sr * sr + si * si;
         // scale by conj(s) / (|s| ||y||); plain 1/||y|| if s vanishes
         const bool gauge = s2 > 1e-30f * n2;
@@ -449,15 +669,23 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
         // ulp each), which cannot overflow where n2 * s2 would
         const float sc = __builtin_amdgcn_rsqf(n2) * (gauge ? __builtin_amdgcn_rsqf(s2) : 1.0f);
         const float2 u = gauge ? make_float2(sr * sc, -si * sc) : make_float2(sc, 0.f);
-        y = cmul(y, u);
-        const float dx = y.x - x.x, dy = y.y - x.y;
-        const float d2 = gsum<NP>(dx * dx + dy * dy);
+        float d2 = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            y[r] = cmul(y[r], u);
+            const float dx = y[r].x - x[r].x, dy = y[r].y - x[r].y;
+            d2 += dx * dx + dy * dy;
+        }
+        d2 = gsum<NP>(d2);
         const bool finite = n2 > 0.f && n2 <= 3.4e38f;
         // slow contraction: |dx| shrank by less than kRefineRate over the
         // last step (always true until two steps are known)
         const bool slow_rate = !(d2prev > 0.f) || d2 > kRefineRate * kRefineRate * d2prev;
         if (!conv) {
-            if (finite) x = y;
+            if (finite) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) x[r] = y[r];
+            }
             // converged: the step is below the tolerance, or the iteration
             // contracts at rate q < 1/2 and the remaining error, at most
             // |dx| q / (1 - q) <= 2 |dx| q, is below 2e-6:
@@ -475,10 +703,19 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
             // rejects it.
             const bool slow = !conv && slow_rate;
             if (gany<64>(slow, 0)) {
-                const float2 bx = group_matvec_lds<NP, NJ>(bme, x, i, xb);
-                const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
-                const float rx = bx.x - rho * x.x, ry = bx.y - rho * x.y;
-                const float res = sqrtf(gsum<NP>(rx * rx + ry * ry));
+                float2 bx[R];
+                bv.apply(x, bx);
+                float rho = 0.f;
+#pragma unroll
+                for (int r = 0; r < R; ++r) rho += x[r].x * bx[r].x + x[r].y * bx[r].y;
+                rho = gsum<NP>(rho);
+                float res2 = 0.f;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float rx = bx[r].x - rho * x[r].x, ry = bx[r].y - rho * x[r].y;
+                    res2 += rx * rx + ry * ry;
+                }
+                const float res = sqrtf(gsum<NP>(res2));
                 if (slow && rho - res > mu) {
                     rho_t = rho;
                     res_t = res;
@@ -490,7 +727,15 @@ __device__ __forceinline__ void eig_min(float2 (&m)[NJ], const float2* bme, floa
             }
         }
     }
+}
 
+// One row per lane, B's rows element-major in LDS at bme[j * kBlock].
+template <int NP, int NJ>
+__device__ __forceinline__ void eig_min(float2 (&m)[1][NJ], float2* bme, float bnorm2, float mu, bool solve, int N,
+                                        int i, float2* rbc0, float2* rbc1, float2* xb, float2 (&x)[1], bool& conv,
+                                        int& it, int& retries) {
+    const BRowLds<NP, NJ> bv{bme, xb, i};
+    eig_min_r<NP, 1, NJ>(m, bv, bnorm2, mu, solve, N, i, rbc0, rbc1, xb, x, conv, it, retries);
 }
 
 }  // namespace

@@ -139,11 +139,15 @@ __global__ __launch_bounds__(kBlock) void link_vjp_kernel(VjpArgs a) {
         bme[j * kBlock] = v;
         bnorm2 += v.x * v.x + v.y * v.y;
     }
-    float2 m[NJ];
+    float2 m[1][NJ];
     bool conv;
     int it, retries;
-    eig_min<NP, NJ>(m, bme, bnorm2, emi ? 0.99f : evd_shift, !skip, N, i, rbc0, rbc1, xb, x, conv, it,
-                    retries);
+    {
+        float2 xv[1] = {x};
+        eig_min<NP, NJ>(m, bme, bnorm2, emi ? 0.99f : evd_shift, !skip, N, i, rbc0, rbc1, xb, xv, conv, it,
+                        retries);
+        x = xv[0];
+    }
     const float2 bx = matvec_lds<NJ>(bme, x, i, xb);
     const float lam = gsum<NP>(x.x * bx.x + x.y * bx.y);
 

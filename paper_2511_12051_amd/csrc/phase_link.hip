@@ -1,10 +1,11 @@
 // EMI phase linking with EVD fallback (paper Sec. 3.2, eq.
 // emi-eigenvalue-problem) and the reference gauge of Sec. 2.1.
 //
-// Layout: a group of NP = 16 or 32 lanes owns one pixel, lane i holds row i of
-// every matrix in registers (NP <= 32 images), so a wavefront solves 4 or 2
-// pixels side by side.  The pivot row of each Gauss-Jordan step and the
-// current iterate are broadcast through a few hundred bytes of LDS per group.
+// Layout: a group of 16 lanes (one DPP row) owns one pixel and lane l holds
+// rows l and, for N > 16, l + 16 of every matrix in registers (N <= 32
+// images), so a wavefront solves 4 pixels side by side.  The pivot row of
+// each Gauss-Jordan step and the current iterate move between the lanes of a
+// group by DPP row broadcasts; B is kept in LDS between factorisations.
 //
 //  1. G = |C| in FP64; in-place Gauss-Jordan inversion.  Its pivots are the
 //     LDL^T pivots of G; one <= 1e-6 (or not finite) means the inversion
@@ -23,6 +24,7 @@
 //     the eigen-gap is small compared with the distance from 0.99.
 //  4. zeta_i = x_i conj(x_ref), returned as unit phasors.
 #include <cmath>
+#include <utility>
 
 #include "batch_device.hpp"
 #include "eig_device.hpp"
@@ -32,127 +34,231 @@ namespace {
 
 
 
-template <int NP, int NJ>
+template <int R, int NJ>
 __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
-    constexpr int GPW = 64 / NP;  // groups (pixels) per wavefront
+    constexpr int GPW = 4;  // 16-lane groups (pixels) per wavefront
     // NJ >= N columns are stored and updated per row (N rounded up to a
-    // multiple of 4); NP >= N lanes hold the rows.
-    // per group: two GJ pivot-row buffers (NJ + 2 doubles each, also used as
-    // NJ + 2 float2) and the iterate buffer (NP float2)
-    constexpr int ROW_BYTES = (NJ + 2) * 8;
-    constexpr int GROUP_BYTES = 2 * ROW_BYTES + NP * 8;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[(kBlock / 64) * GPW * GROUP_BYTES];
-    // row i of B for every lane, element-major so that the lanes of a
-    // wavefront read consecutive words: read back for refactorisations and
-    // Rayleigh quotients instead of occupying registers through the iteration
-    __shared__ __attribute__((aligned(16))) float2 brow[NJ][kBlock];
-    const int lane = lane_id();
-    const int i = lane & (NP - 1);
-    const int grp = lane / NP;
+    // multiple of 4); lane l of a group holds rows l and, for R = 2, l + 16.
+    // Between factorisations B lives in LDS: one row per lane element-major
+    // (R = 1), or the packed upper triangle of each group's matrix (R = 2),
+    // which is also where B is formed from C.
+    using Tri = BTriLds<NJ>;
+    constexpr int LDS_BYTES = R == 1 ? NJ * kBlock * 8 : (kBlock / 64) * Tri::WAVE_ENTRIES * 8;
+    __shared__ __attribute__((aligned(16))) float2 lds[LDS_BYTES / 8];
+    // opaque copies of the lane index and N: in a persistent loop the
+    // compiler would otherwise precompute every per-step constant and
+    // predicate once and keep them live (in spilled registers) across it
+    const int lane = opaque_int(lane_id());
+    const int l = lane & 15;
+    const int grp = lane >> 4;
     const int wave = threadIdx.x >> 6;
-    unsigned char* gbase = lds + (wave * GPW + grp) * GROUP_BYTES;
-    double* rbd0 = reinterpret_cast<double*>(gbase);
-    double* rbd1 = reinterpret_cast<double*>(gbase + ROW_BYTES);
-    float2* rbc0 = reinterpret_cast<float2*>(gbase);
-    float2* rbc1 = reinterpret_cast<float2*>(gbase + ROW_BYTES);
-    float2* xb = reinterpret_cast<float2*>(gbase + 2 * ROW_BYTES);
 
-    const int N = a.N;
+    const int N = opaque_uniform(__builtin_amdgcn_readfirstlane(a.N));
     const int64_t pix = (block * (kBlock / 64) + wave) * GPW + grp;
     const bool active = pix < a.npix;
-    const bool row_live = active && i < N;
-
-    // ---- row i of C (each lane reads its own row; a variant staging the
-    // wavefront's matrices through LDS with coalesced loads measured slower)
-    const int NN = N * N;
-    const float2* src = a.coh + (active ? pix : 0) * (int64_t)NN + (int64_t)i * N;
-    float2 c[NJ];
+    bool live[R];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
+    for (int r = 0; r < R; ++r) live[r] = active && l + 16 * r < N;
+
+    // ---- rows of C (each lane reads its own rows; a variant staging the
+    // wavefront's matrices through LDS with coalesced loads measured slower)
+    // Loads are issued for every slot at clamped, in-bounds addresses and the
+    // values selected afterwards: a load inside a per-entry branch waits for
+    // its data before the next one is issued.
+    const float2* mat = a.coh + (active ? pix : 0) * (int64_t)(N * N);
+    const float2* src = mat + (int64_t)min(l, N - 1) * N;  // row l (clamped)
+    float2 c[R][NJ];
+    if constexpr (R == 1) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const float2 v = src[min(j, N - 1)];
+            c[0][j] = (live[0] && j < N) ? v : make_float2(0.f, 0.f);
+        }
+    } else {
+        // Two rows per lane keep B as an upper triangle, so C is taken as the
+        // Hermitian matrix its upper triangle defines: entry (i, j < i) is
+        // conj(C[j][i]).  A computed C is Hermitian only to rounding, and for
+        // an ill-conditioned |C| the inverses of its two triangles differ by
+        // far more than that; with G = |C| exactly symmetric, G^{-1} is
+        // symmetric to its own rounding and the triangle of B is consistent.
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = min(l + 16 * r, N - 1);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int jc = min(j, N - 1);
+                float2 v = mat[min(i, jc) * N + max(i, jc)];  // entry (min, max): no branch
+                v.y = jc < i ? -v.y : v.y;
+                c[r][j] = (live[r] && j < N) ? v : make_float2(0.f, 0.f);
+            }
+        }
+    }
     bool bad = false;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) bad = bad || !(fabsf(c[j].x) <= 3.4e38f && fabsf(c[j].y) <= 3.4e38f);
-    const bool invalid = !active || gany<NP>(bad, grp);
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) bad = bad | !(fabsf(c[r][j].x) <= 3.4e38f && fabsf(c[r][j].y) <= 3.4e38f);  // no short circuit: no branches
+    const bool invalid = !active || gany<16>(bad, grp);
 
     // start from column ref of C: the single-reference interferogram phases
-    float2 x = make_float2(0.f, 0.f);
+    float2 x[R];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-        if (j == a.ref && row_live) x = c[j];
+    for (int r = 0; r < R; ++r) {
+        x[r] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            if (j == a.ref && live[r]) x[r] = c[r][j];
+    }
     {
         // unit-modulus start: the phases of column ref (for consistent phases
         // the EMI eigenvector has entries of equal modulus)
-        const float x2 = x.x * x.x + x.y * x.y;
-        if (x2 > 0.f) {
-            const float r = __builtin_amdgcn_rsqf(x2);
-            x.x *= r;
-            x.y *= r;
+        float nrm = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float x2 = x[r].x * x[r].x + x[r].y * x[r].y;
+            if (x2 > 0.f) {
+                const float q = __builtin_amdgcn_rsqf(x2);
+                x[r].x *= q;
+                x[r].y *= q;
+            }
+            nrm += x[r].x * x[r].x + x[r].y * x[r].y;
         }
-        float nrm = gsum<NP>(x.x * x.x + x.y * x.y);
+        nrm = gsum<16>(nrm);
         if (!(nrm > 0.f)) {
-            x = make_float2(i == a.ref ? 1.f : 0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = make_float2(l + 16 * r == a.ref ? 1.f : 0.f, 0.f);
             nrm = 1.f;
         }
-        const float s = __builtin_amdgcn_rsqf(nrm);
-        x.x *= s;
-        x.y *= s;
+        const float q = __builtin_amdgcn_rsqf(nrm);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            x[r].x *= q;
+            x[r].y *= q;
+        }
+    }
+    const Tri tri{lds + wave * Tri::WAVE_ENTRIES, grp, l, N};
+    if constexpr (R == 2) {
+        // C's upper triangle goes to LDS now; B is formed there after step 1
+        const int ub[2] = {tri.up_base(l, 0), tri.up_base(l, 1)};
+        [&]<int... J>(std::integer_sequence<int, J...>) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) ((tri.w[tri.template own<J>(ub[r], l, r, N)] = c[r][J]), ...);
+        }(std::make_integer_sequence<int, NJ>{});
     }
     // ---- 1. FP64 inverse of G = |C|
     bool use_evd = a.method == PL_LINK_EVD;
-    double gi[NJ];
+    double gi[R][NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) gi[j] = (row_live && j < N) ? cabs64(c[j].x, c[j].y) : 0.0;
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) gi[r][j] = (live[r] && j < N) ? cabs64(c[r][j].x, c[r][j].y) : 0.0;
     const bool do_emi = !use_evd && !invalid;
-    const bool gfail = factor_g<NP, NJ>(gi, N, i, do_emi, rbd0, rbd1);
+    const bool gfail = factor_g<16, R, NJ>(gi, N, l, do_emi, nullptr, nullptr);
     use_evd = use_evd || gfail;
 
-    // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted.  Row i
-    // of C is read again (an L2 hit) rather than kept live across step 1.
+    // ---- 2. the Hermitian matrix whose smallest eigenpair is wanted,
+    // B = G^{-1} o C (EMI) or -C (EVD), and ||B||_F^2 (per lane, summed by
+    // the solver)
+    float bnorm2 = 0.f;
+    if constexpr (R == 1) {
+        // row i of C is read again (an L2 hit) rather than kept live across step 1
+        const float2* src2 = src + opaque_int(0);
+        float2* bme = lds + threadIdx.x;  // element j at bme[j * kBlock]
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) c[j] = (row_live && j < N) ? src[j] : make_float2(0.f, 0.f);
-    float2* bme = &brow[0][threadIdx.x];  // element j at bme[j * kBlock]
-    float bnorm2 = 0.f;  // ||row i of B||^2
+        for (int j = 0; j < NJ; ++j) {
+            const float2 cl = src2[min(j, N - 1)];
+            const float2 cj = (live[0] && j < N) ? cl : make_float2(0.f, 0.f);
+            const float2 v = use_evd ? make_float2(-cj.x, -cj.y)
+                                     : make_float2((float)gi[0][j] * cj.x, (float)gi[0][j] * cj.y);
+            bme[j * kBlock] = v;
+            bnorm2 = fmaf(v.x, v.x, fmaf(v.y, v.y, bnorm2));
+        }
+    } else {
+        // in place over the upper triangle: each lane rewrites the entries it
+        // owns (i, j >= i); off-diagonal entries count twice in ||B||_F^2
+        const int ub[2] = {tri.up_base(l, 0), tri.up_base(l, 1)};
+        [&]<int... J>(std::integer_sequence<int, J...>) {
+            auto one = [&](auto jc, int r) __attribute__((always_inline)) {
+                constexpr int j = decltype(jc)::value;
+                const int o = tri.template own<j>(ub[r], l, r, N);
+                const float2 cv = tri.w[o];
+                const float gv = (float)gi[r][j];
+                const float2 v = use_evd ? make_float2(-cv.x, -cv.y) : make_float2(gv * cv.x, gv * cv.y);
+                tri.w[o] = v;
+                const float wgt = (o == tri.sink()) ? 0.f : (j == l + 16 * r ? 1.f : 2.f);
+                bnorm2 = fmaf(wgt * v.x, v.x, fmaf(wgt * v.y, v.y, bnorm2));
+            };
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        float2 v;
-        if (use_evd) v = make_float2(-c[j].x, -c[j].y);
-        else v = make_float2((float)gi[j] * c[j].x, (float)gi[j] * c[j].y);
-        bme[j * kBlock] = v;
-        bnorm2 += v.x * v.x + v.y * v.y;
+            for (int r = 0; r < R; ++r) (one(std::integral_constant<int, J>{}, r), ...);
+        }(std::make_integer_sequence<int, NJ>{});
     }
     float mu = 0.99f;
-    if (use_evd) {
+    if (gany<64>(use_evd, 0)) {
         // EVD shift: minus a Gershgorin bound on lambda_max(C), so -C - mu I > 0
+        float2 brow[R][NJ];
+        if constexpr (R == 1) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) brow[0][j] = lds[threadIdx.x + j * kBlock];
+        } else {
+            tri.load(brow, true);
+        }
         float rs = 0.f;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) rs += __builtin_amdgcn_sqrtf(c[j].x * c[j].x + c[j].y * c[j].y);
-        mu = -(1.0f + 1e-3f) * gmax<NP>(rs) - 1e-3f;
+        for (int r = 0; r < R; ++r) {
+            float rsr = 0.f;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                rsr += __builtin_amdgcn_sqrtf(brow[r][j].x * brow[r][j].x + brow[r][j].y * brow[r][j].y);
+            rs = fmaxf(rs, rsr);
+        }
+        rs = gmax<16>(rs);
+        if (use_evd) mu = -(1.0f + 1e-3f) * rs - 1e-3f;
     }
 
     // ---- 3. shifted inverse iteration
-    float2 m[NJ];
+    float2 m[R][NJ];
     bool conv;
     int it, retries;
-    eig_min<NP, NJ>(m, bme, bnorm2, mu, !invalid, N, i, rbc0, rbc1, xb, x, conv, it, retries);
+    float2 bx[R];
+    if constexpr (R == 1) {
+        const BRowLds<16, NJ> bv{lds + threadIdx.x, nullptr, l};
+        eig_min_r<16, 1, NJ>(m, bv, bnorm2, mu, !invalid, N, l, nullptr, nullptr, nullptr, x, conv, it, retries);
+        bv.apply(x, bx);
+    } else {
+        eig_min_r<16, R, NJ>(m, tri, bnorm2, mu, !invalid, N, l, nullptr, nullptr, nullptr, x, conv, it, retries);
+        tri.apply(x, bx);
+    }
 
     // ---- 4. eigenvalue, reference and unit phasors
-    const float2 bx = group_matvec_lds<NP, NJ>(bme, x, i, xb);
-    const float rho = gsum<NP>(x.x * bx.x + x.y * bx.y);
-    const float2 xr = make_float2(__shfl(x.x, grp * NP + a.ref, 64), __shfl(x.y, grp * NP + a.ref, 64));
-    float2 z = make_float2(x.x * xr.x + x.y * xr.y, x.y * xr.x - x.x * xr.y);  // x conj(x_ref)
-    const float z2 = z.x * z.x + z.y * z.y;
-    const float zi = __builtin_amdgcn_rsqf(z2);
-    float2 phv = (z2 > 0.f && !invalid) ? make_float2(z.x * zi, z.y * zi) : make_float2(1.f, 0.f);
-    if (i == a.ref) phv = make_float2(1.f, 0.f);
-    if (row_live) a.ph[(int64_t)i * a.npix + pix] = phv;
-    if (row_live && a.phase) a.phase[(int64_t)i * a.npix + pix] = (i == a.ref || invalid) ? 0.f : atan2f(phv.y, phv.x);
+    float rho = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) rho += x[r].x * bx[r].x + x[r].y * bx[r].y;
+    rho = gsum<16>(rho);
+    float2 xs = x[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r)
+        if (a.ref >= 16 * r) xs = x[r];
+    const int src_lane = grp * 16 + (a.ref & 15);
+    const float2 xr = make_float2(__shfl(xs.x, src_lane, 64), __shfl(xs.y, src_lane, 64));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = l + 16 * r;
+        float2 z = make_float2(x[r].x * xr.x + x[r].y * xr.y, x[r].y * xr.x - x[r].x * xr.y);  // x conj(x_ref)
+        const float z2 = z.x * z.x + z.y * z.y;
+        const float zi = __builtin_amdgcn_rsqf(z2);
+        float2 phv = (z2 > 0.f && !invalid) ? make_float2(z.x * zi, z.y * zi) : make_float2(1.f, 0.f);
+        if (i == a.ref) phv = make_float2(1.f, 0.f);
+        if (live[r]) a.ph[(int64_t)i * a.npix + pix] = phv;
+        if (live[r] && a.phase)
+            a.phase[(int64_t)i * a.npix + pix] = (i == a.ref || invalid) ? 0.f : atan2f(phv.y, phv.x);
+    }
     const uint8_t flag = invalid ? PL_FLAG_INVALID : (use_evd ? PL_FLAG_EVD : PL_FLAG_EMI);
-    if (active && i == 0) {
+    if (active && l == 0) {
         if (a.lam) a.lam[pix] = invalid ? __builtin_nanf("") : (use_evd ? -rho : rho);
         if (a.flags) a.flags[pix] = flag;
     }
     if (a.counters) {
-        const bool lead = active && i == 0;
+        const bool lead = active && l == 0;
         const uint64_t e = __ballot(lead && flag == PL_FLAG_EVD);
         const uint64_t v = __ballot(lead && flag == PL_FLAG_INVALID);
         const uint64_t nc = __ballot(lead && !conv);
@@ -168,43 +274,43 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     }
 }
 
-// 32-lane groups (N > 16) run persistently: the grid (a few times the
-// resident workgroups) strides over the pixel blocks, which avoids
-// dispatching hundreds of thousands of short workgroups; 16-lane groups keep
+// Groups with two rows per lane (N > 16) run persistently: the grid (a few
+// times the resident workgroups) strides over the pixel blocks, which avoids
+// dispatching hundreds of thousands of short workgroups; one-row groups keep
 // one block per workgroup, where the loop would cost the occupancy-4
 // register budget
-template <int NP, int NJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 4 : 1, NP == 16 ? 4 : 2)))
+template <int R, int NJ>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == 1 ? 4 : 1, R == 1 ? 4 : 1)))
 void phase_link_kernel(LinkArgs a, int64_t blocks) {
-    if constexpr (NP == 16) {
-        link_body<NP, NJ>(a, blockIdx.x);
+    if constexpr (R == 1) {
+        link_body<R, NJ>(a, blockIdx.x);
     } else {
-        for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) link_body<NP, NJ>(a, b);
+        for (int64_t b = blockIdx.x; b < blocks; b += gridDim.x) link_body<R, NJ>(a, b);
     }
 }
 
 // the stride loop needs a few registers more than 128: allow occupancy 3 for
-// 16-lane groups rather than spilling
-template <int NP, int NJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NP == 16 ? 3 : 1, NP == 16 ? 4 : 2)))
+// one-row groups rather than spilling
+template <int R, int NJ>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == 1 ? 3 : 1, R == 1 ? 4 : 1)))
 void phase_link_batch(BatchRange<LinkArgs> r) {
     // groups of a block never synchronise with each other, so consecutive
     // blocks of the stride loop need no barrier
     for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
         const int k = batch_item(r.starts, r.n, b);
-        link_body<NP, NJ>(r.items[k], b - r.starts[k]);
+        link_body<R, NJ>(r.items[k], b - r.starts[k]);
     }
 }
 
 }  // namespace
 
 int64_t link_blocks(int N, int64_t npix) {
-    const int np = N <= 16 ? 16 : 32;
-    const int64_t per_block = (kBlock / 64) * (64 / np);
+    (void)N;
+    const int64_t per_block = (kBlock / 64) * 4;  // four 16-lane groups per wavefront
     return (npix + per_block - 1) / per_block;
 }
 
-template <int NP, int NJ>
+template <int R, int NJ>
 pl_status launch_persistent(const LinkArgs& a, int64_t blocks, hipStream_t s) {
     // resident workgroups per CU of this variant, per device (queried once)
     static int per_cu[64] = {0};
@@ -213,18 +319,18 @@ pl_status launch_persistent(const LinkArgs& a, int64_t blocks, hipStream_t s) {
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
     if (!per_cu[dev]) {
         int n = 0, c = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(phase_link_kernel<NP, NJ>),
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(phase_link_kernel<R, NJ>),
                                                          kBlock, 0) != hipSuccess || n < 1)
             n = 1;
         if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 1;
         cus[dev] = c;
         per_cu[dev] = n;
     }
-    int64_t grid = NP == 16 ? blocks : (int64_t)per_cu[dev] * cus[dev] * 4;
+    int64_t grid = R == 1 ? blocks : (int64_t)per_cu[dev] * cus[dev] * 4;
     if (grid > blocks) grid = blocks;
     if (grid > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link: too many pixels");
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((phase_link_kernel<NP, NJ>), dim3((unsigned)grid), dim3(kBlock), 0, s, a, blocks);
+    hipLaunchKernelGGL((phase_link_kernel<R, NJ>), dim3((unsigned)grid), dim3(kBlock), 0, s, a, blocks);
     return launch_ok("phase linking kernel");
 }
 
@@ -234,23 +340,23 @@ pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int
     LinkArgs a{coh, N, npix, ref, method, phasors, phase, lambda, flags, counters};
     const int64_t blocks = link_blocks(N, npix);
     switch ((N + 3) / 4) {  // columns per row: N rounded up to a multiple of 4
-        case 1: case 2: case 3: return launch_persistent<16, 12>(a, blocks, s);
-        case 4: return launch_persistent<16, 16>(a, blocks, s);
-        case 5: return launch_persistent<32, 20>(a, blocks, s);
-        case 6: return launch_persistent<32, 24>(a, blocks, s);
-        case 7: return launch_persistent<32, 28>(a, blocks, s);
-        default: return launch_persistent<32, 32>(a, blocks, s);
+        case 1: case 2: case 3: return launch_persistent<1, 12>(a, blocks, s);
+        case 4: return launch_persistent<1, 16>(a, blocks, s);
+        case 5: return launch_persistent<2, 20>(a, blocks, s);
+        case 6: return launch_persistent<2, 24>(a, blocks, s);
+        case 7: return launch_persistent<2, 28>(a, blocks, s);
+        default: return launch_persistent<2, 32>(a, blocks, s);
     }
 }
 
 const void* phase_link_batch_fn(int N_class) {
     switch (N_class) {
-        case 1: case 2: case 3: return reinterpret_cast<const void*>(phase_link_batch<16, 12>);
-        case 4: return reinterpret_cast<const void*>(phase_link_batch<16, 16>);
-        case 5: return reinterpret_cast<const void*>(phase_link_batch<32, 20>);
-        case 6: return reinterpret_cast<const void*>(phase_link_batch<32, 24>);
-        case 7: return reinterpret_cast<const void*>(phase_link_batch<32, 28>);
-        default: return reinterpret_cast<const void*>(phase_link_batch<32, 32>);
+        case 1: case 2: case 3: return reinterpret_cast<const void*>(phase_link_batch<1, 12>);
+        case 4: return reinterpret_cast<const void*>(phase_link_batch<1, 16>);
+        case 5: return reinterpret_cast<const void*>(phase_link_batch<2, 20>);
+        case 6: return reinterpret_cast<const void*>(phase_link_batch<2, 24>);
+        case 7: return reinterpret_cast<const void*>(phase_link_batch<2, 28>);
+        default: return reinterpret_cast<const void*>(phase_link_batch<2, 32>);
     }
 }
 
@@ -258,12 +364,12 @@ pl_status launch_phase_link_batch(const BatchRange<LinkArgs>& r, int N_class, in
     if (r.total == 0) return PL_OK;
     const dim3 gr((unsigned)grid), block(kBlock);
     switch (N_class) {  // (N + 3) / 4, shared by every item of the range
-        case 1: case 2: case 3: hipLaunchKernelGGL((phase_link_batch<16, 12>), gr, block, 0, s, r); break;
-        case 4: hipLaunchKernelGGL((phase_link_batch<16, 16>), gr, block, 0, s, r); break;
-        case 5: hipLaunchKernelGGL((phase_link_batch<32, 20>), gr, block, 0, s, r); break;
-        case 6: hipLaunchKernelGGL((phase_link_batch<32, 24>), gr, block, 0, s, r); break;
-        case 7: hipLaunchKernelGGL((phase_link_batch<32, 28>), gr, block, 0, s, r); break;
-        default: hipLaunchKernelGGL((phase_link_batch<32, 32>), gr, block, 0, s, r); break;
+        case 1: case 2: case 3: hipLaunchKernelGGL((phase_link_batch<1, 12>), gr, block, 0, s, r); break;
+        case 4: hipLaunchKernelGGL((phase_link_batch<1, 16>), gr, block, 0, s, r); break;
+        case 5: hipLaunchKernelGGL((phase_link_batch<2, 20>), gr, block, 0, s, r); break;
+        case 6: hipLaunchKernelGGL((phase_link_batch<2, 24>), gr, block, 0, s, r); break;
+        case 7: hipLaunchKernelGGL((phase_link_batch<2, 28>), gr, block, 0, s, r); break;
+        default: hipLaunchKernelGGL((phase_link_batch<2, 32>), gr, block, 0, s, r); break;
     }
     return launch_ok("batched phase linking kernel");
 }
