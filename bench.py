@@ -153,10 +153,11 @@ def roofline(alg, t_ms):
 def kernel_name(stage, wl, prec):
     """Device kernel that runs a stage (as rocprofv3 names it, without spaces)."""
     tile = 16 if wl.N <= 16 else 32
+    rows = 1 if wl.N <= 16 else 2          # rows per lane of the linking kernel's 16-lane groups
     cols = max(12, 4 * ((wl.N + 3) // 4))  # columns per row of the linking kernel
     return {"stats": "amp_stats_vec", "glrt": "glrt_kernel",
             "coherence": f"coherence_kernel<{tile},{'true' if prec == 'bf16' else 'false'}>",
-            "link": f"phase_link_kernel<{tile},{cols}>", "compress": "compress_kernel"}[stage]
+            "link": f"phase_link_kernel<{rows},{cols}>", "compress": "compress_kernel"}[stage]
 
 
 def source_hash(name):
