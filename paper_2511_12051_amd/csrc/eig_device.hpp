@@ -647,82 +647,86 @@ __device__ __forceinline__ void eig_min_r(float2 (&m)[R][NJ], const BV& bv, floa
                     }
                 }
             }
-            continue;
         }
-        if (!gany<64>(!conv, 0) || it >= kMaxIter) break;
-        float2 y[R];
-        group_matvec<NP, R, NJ>(m, x, y, i, xb);
-        float n2 = 0.f, sr = 0.f, si = 0.f;
+        // Iterate in the same pass once no group waits for a factorisation.
+        // (Going back to the loop head after factoring, with `continue`, made
+        // the compiler keep two register copies of m across the loop.)
+        if (!gany<64>(need, 0)) {
+            if (!gany<64>(!conv, 0) || it >= kMaxIter) break;
+            float2 y[R];
+            group_matvec<NP, R, NJ>(m, x, y, i, xb);
+            float n2 = 0.f, sr = 0.f, si = 0.f;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            n2 += y[r].x * y[r].x + y[r].y * y[r].y;
-            sr += x[r].x * y[r].x + x[r].y * y[r].y;  // s = x^H y
-            si += x[r].x * y[r].y - x[r].y * y[r].x;
-        }
-        n2 = gsum<NP>(n2);
-        sr = gsum<NP>(sr);
-        si = gsum<NP>(si);
-        const float s2 = sr * sr + si * si;
-        // scale by conj(s) / (|s| ||y||); plain 1/||y|| if s vanishes
-        const bool gauge = s2 > 1e-30f * n2;
-        // 1 / (||y|| |s|) as a product of two reciprocal square roots (about 1
-        // ulp each), which cannot overflow where n2 * s2 would
-        const float sc = __builtin_amdgcn_rsqf(n2) * (gauge ? __builtin_amdgcn_rsqf(s2) : 1.0f);
-        const float2 u = gauge ? make_float2(sr * sc, -si * sc) : make_float2(sc, 0.f);
-        float d2 = 0.f;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            y[r] = cmul(y[r], u);
-            const float dx = y[r].x - x[r].x, dy = y[r].y - x[r].y;
-            d2 += dx * dx + dy * dy;
-        }
-        d2 = gsum<NP>(d2);
-        const bool finite = n2 > 0.f && n2 <= 3.4e38f;
-        // slow contraction: |dx| shrank by less than kRefineRate over the
-        // last step (always true until two steps are known)
-        const bool slow_rate = !(d2prev > 0.f) || d2 > kRefineRate * kRefineRate * d2prev;
-        if (!conv) {
-            if (finite) {
-#pragma unroll
-                for (int r = 0; r < R; ++r) x[r] = y[r];
+            for (int r = 0; r < R; ++r) {
+                n2 += y[r].x * y[r].x + y[r].y * y[r].y;
+                sr += x[r].x * y[r].x + x[r].y * y[r].y;  // s = x^H y
+                si += x[r].x * y[r].y - x[r].y * y[r].x;
             }
-            // converged: the step is below the tolerance, or the iteration
-            // contracts at rate q < 1/2 and the remaining error, at most
-            // |dx| q / (1 - q) <= 2 |dx| q, is below 2e-6:
-            // d2 < d2prev / 4 and d2 * q^2 = d2^2 / d2prev < (1e-6)^2
-            if (d2 < kTol2 || !finite) conv = true;
-            else if (d2prev > 0.f && d2 < 0.25f * d2prev && d2 * d2 < 1e-12f * d2prev) conv = true;
-            d2prev = d2;
-        }
-        ++it;
-        if (it == 4 || it == 8 || it == 12 || it == 18) {
-            // slow contraction: move the shift towards lambda_min.  The first
-            // candidate rho - ||Bx - rho x|| bounds the eigenvalue nearest rho
-            // from below; while x still mixes several eigenvectors it can lie
-            // above lambda_min, so larger margins follow if the inertia check
-            // rejects it.
-            const bool slow = !conv && slow_rate;
-            if (gany<64>(slow, 0)) {
-                float2 bx[R];
-                bv.apply(x, bx);
-                float rho = 0.f;
+            n2 = gsum<NP>(n2);
+            sr = gsum<NP>(sr);
+            si = gsum<NP>(si);
+            const float s2 = sr * sr + si * si;
+            // scale by conj(s) / (|s| ||y||); plain 1/||y|| if s vanishes
+            const bool gauge = s2 > 1e-30f * n2;
+            // 1 / (||y|| |s|) as a product of two reciprocal square roots (about 1
+            // ulp each), which cannot overflow where n2 * s2 would
+            const float sc = __builtin_amdgcn_rsqf(n2) * (gauge ? __builtin_amdgcn_rsqf(s2) : 1.0f);
+            const float2 u = gauge ? make_float2(sr * sc, -si * sc) : make_float2(sc, 0.f);
+            float d2 = 0.f;
 #pragma unroll
-                for (int r = 0; r < R; ++r) rho += x[r].x * bx[r].x + x[r].y * bx[r].y;
-                rho = gsum<NP>(rho);
-                float res2 = 0.f;
+            for (int r = 0; r < R; ++r) {
+                y[r] = cmul(y[r], u);
+                const float dx = y[r].x - x[r].x, dy = y[r].y - x[r].y;
+                d2 += dx * dx + dy * dy;
+            }
+            d2 = gsum<NP>(d2);
+            const bool finite = n2 > 0.f && n2 <= 3.4e38f;
+            // slow contraction: |dx| shrank by less than kRefineRate over the
+            // last step (always true until two steps are known)
+            const bool slow_rate = !(d2prev > 0.f) || d2 > kRefineRate * kRefineRate * d2prev;
+            if (!conv) {
+                if (finite) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const float rx = bx[r].x - rho * x[r].x, ry = bx[r].y - rho * x[r].y;
-                    res2 += rx * rx + ry * ry;
+                    for (int r = 0; r < R; ++r) x[r] = y[r];
                 }
-                const float res = sqrtf(gsum<NP>(res2));
-                if (slow && rho - res > mu) {
-                    rho_t = rho;
-                    res_t = res;
-                    cand = 0;
-                    mu_req = rho - res;
-                    need = true;
-                    stage = 4;
+                // converged: the step is below the tolerance, or the iteration
+                // contracts at rate q < 1/2 and the remaining error, at most
+                // |dx| q / (1 - q) <= 2 |dx| q, is below 2e-6:
+                // d2 < d2prev / 4 and d2 * q^2 = d2^2 / d2prev < (1e-6)^2
+                if (d2 < kTol2 || !finite) conv = true;
+                else if (d2prev > 0.f && d2 < 0.25f * d2prev && d2 * d2 < 1e-12f * d2prev) conv = true;
+                d2prev = d2;
+            }
+            ++it;
+            if (it == 4 || it == 8 || it == 12 || it == 18) {
+                // slow contraction: move the shift towards lambda_min.  The first
+                // candidate rho - ||Bx - rho x|| bounds the eigenvalue nearest rho
+                // from below; while x still mixes several eigenvectors it can lie
+                // above lambda_min, so larger margins follow if the inertia check
+                // rejects it.
+                const bool slow = !conv && slow_rate;
+                if (gany<64>(slow, 0)) {
+                    float2 bx[R];
+                    bv.apply(x, bx);
+                    float rho = 0.f;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) rho += x[r].x * bx[r].x + x[r].y * bx[r].y;
+                    rho = gsum<NP>(rho);
+                    float res2 = 0.f;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float rx = bx[r].x - rho * x[r].x, ry = bx[r].y - rho * x[r].y;
+                        res2 += rx * rx + ry * ry;
+                    }
+                    const float res = sqrtf(gsum<NP>(res2));
+                    if (slow && rho - res > mu) {
+                        rho_t = rho;
+                        res_t = res;
+                        cand = 0;
+                        mu_req = rho - res;
+                        need = true;
+                        stage = 4;
+                    }
                 }
             }
         }

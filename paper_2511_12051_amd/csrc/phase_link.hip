@@ -75,12 +75,9 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
             c[0][j] = (live[0] && j < N) ? v : make_float2(0.f, 0.f);
         }
     } else {
-        // Two rows per lane keep B as an upper triangle, so C is taken as the
-        // Hermitian matrix its upper triangle defines: entry (i, j < i) is
-        // conj(C[j][i]).  A computed C is Hermitian only to rounding, and for
-        // an ill-conditioned |C| the inverses of its two triangles differ by
-        // far more than that; with G = |C| exactly symmetric, G^{-1} is
-        // symmetric to its own rounding and the triangle of B is consistent.
+        // The Hermitian matrix of C's upper triangle (reading R13): entry
+        // (i, j < i) is conj(C[j][i]), so that G = |C| is exactly symmetric
+        // and the triangle of B (below) is consistent.
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = min(l + 16 * r, N - 1);
@@ -177,19 +174,30 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
         // in place over the upper triangle: each lane rewrites the entries it
         // owns (i, j >= i); off-diagonal entries count twice in ||B||_F^2
         const int ub[2] = {tri.up_base(l, 0), tri.up_base(l, 1)};
+        float gf[R][NJ];  // G^{-1} as B uses it, in half the registers
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) gf[r][j] = (float)gi[r][j];
         [&]<int... J>(std::integer_sequence<int, J...>) {
             auto one = [&](auto jc, int r) __attribute__((always_inline)) {
                 constexpr int j = decltype(jc)::value;
                 const int o = tri.template own<j>(ub[r], l, r, N);
                 const float2 cv = tri.w[o];
-                const float gv = (float)gi[r][j];
+                const float gv = gf[r][j];
                 const float2 v = use_evd ? make_float2(-cv.x, -cv.y) : make_float2(gv * cv.x, gv * cv.y);
                 tri.w[o] = v;
                 const float wgt = (o == tri.sink()) ? 0.f : (j == l + 16 * r ? 1.f : 2.f);
                 bnorm2 = fmaf(wgt * v.x, v.x, fmaf(wgt * v.y, v.y, bnorm2));
             };
+            // at most four columns of loads in flight
+            auto four = [&](auto jc) __attribute__((always_inline)) {
+                constexpr int j = decltype(jc)::value;
 #pragma unroll
-            for (int r = 0; r < R; ++r) (one(std::integral_constant<int, J>{}, r), ...);
+                for (int r = 0; r < R; ++r) one(jc, r);
+                if constexpr (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+            };
+            (four(std::integral_constant<int, J>{}), ...);
         }(std::make_integer_sequence<int, NJ>{});
     }
     float mu = 0.99f;
@@ -277,10 +285,12 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
 // Groups with two rows per lane (N > 16) run persistently: the grid (a few
 // times the resident workgroups) strides over the pixel blocks, which avoids
 // dispatching hundreds of thousands of short workgroups; one-row groups keep
-// one block per workgroup, where the loop would cost the occupancy-4
-// register budget
+// one block per workgroup.  Two-row kernels are held to two wavefronts per
+// SIMD: within 256 registers a few dozen values spill, all outside the
+// solver loop, and that measured 28 % faster at 28 columns than one
+// wavefront per SIMD without spills.
 template <int R, int NJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == 1 ? 4 : 1, R == 1 ? 4 : 1)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == 1 ? 4 : 2, R == 1 ? 4 : 2)))
 void phase_link_kernel(LinkArgs a, int64_t blocks) {
     if constexpr (R == 1) {
         link_body<R, NJ>(a, blockIdx.x);
@@ -289,10 +299,10 @@ void phase_link_kernel(LinkArgs a, int64_t blocks) {
     }
 }
 
-// the stride loop needs a few registers more than 128: allow occupancy 3 for
-// one-row groups rather than spilling
+// the stride loop needs more registers: allow occupancy 3 for one-row groups
+// rather than spilling
 template <int R, int NJ>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == 1 ? 3 : 1, R == 1 ? 4 : 1)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(R == 1 ? 3 : 2, R == 1 ? 4 : 2)))
 void phase_link_batch(BatchRange<LinkArgs> r) {
     // groups of a block never synchronise with each other, so consecutive
     // blocks of the stride loop need no barrier
