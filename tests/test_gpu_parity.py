@@ -218,6 +218,49 @@ def test_two_images_closed_form(gpu_lib):
     np.testing.assert_allclose(lam.cpu().numpy(), 1.0, atol=1e-4)
 
 
+def test_upper_triangle_reading_above_16_images(gpu_lib):
+    """For N > 16 the linking kernel takes C as the Hermitian matrix of its
+    upper triangle (two rows per lane keep B as a packed triangle): changing
+    the strictly lower triangle by a few ulp leaves every output bit
+    unchanged, including on ill-conditioned |C|, where the inverses of the
+    two triangles of |C| differ most.  On well-posed pixels the phases match
+    the FP64 oracle on that Hermitian matrix."""
+    rng = np.random.default_rng(31)
+    N, P, ref = 25, 512, 3
+    looks = rng.integers(N + 2, 3 * N, P)
+    Ch = np.empty((P, N, N), np.complex128)
+    for p in range(P):
+        Z = rng.standard_normal((N, looks[p])) + 1j * rng.standard_normal((N, looks[p]))
+        # correlated images; the stronger the common part, the closer |C| gets to singular
+        Z[1:] += [2.0, 6.0, 15.0][p % 3] * Z[:1] * np.exp(1j * rng.uniform(-np.pi, np.pi, (N - 1, 1)))
+        A = Z @ Z.conj().T
+        d = 1.0 / np.sqrt(np.real(np.diag(A)))
+        Ch[p] = A * d[:, None] * d[None, :]
+    Ch = np.triu(Ch, 1) + np.conj(np.swapaxes(np.triu(Ch, 1), 1, 2)) + np.eye(N)
+    Ch = Ch.astype(np.complex64)  # exactly Hermitian in FP32, unit diagonal
+    assert np.array_equal(Ch, np.conj(np.swapaxes(Ch, 1, 2)))
+    Cp = Ch.copy()
+    low = np.tril(np.ones((N, N), bool), -1)
+    ulp = np.float32(2.0 ** -22)
+    Cp[:, low] = (Ch[:, low].real * (1 + ulp * rng.choice([-1, 1], (P, low.sum())))
+                  + 1j * Ch[:, low].imag * (1 + ulp * rng.choice([-1, 1], (P, low.sum())))).astype(np.complex64)
+    assert not np.array_equal(Cp, Ch)
+    out = [gpu_lib.phase_link(torch.from_numpy(c).cuda(), ref=ref) for c in (Ch, Cp)]
+    torch.cuda.synchronize()
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    cond = np.linalg.cond(np.abs(Ch.astype(np.complex128)))
+    orc = O.phase_link(Ch, ref=ref)
+    ph, lam, flags = (t.cpu().numpy() for t in out[0])
+    sens = O.phase_sensitivity(Ch.astype(np.complex128), ref=ref)
+    wp = (SAFETY * sens * EPS_FLOOR <= PHASE_TOL) & (flags == orc["flag"])
+    err = np.abs(np.angle(ph * np.conj(orc["phasor"]))).max(axis=0)
+    print(f"[parity] upper triangle N={N}: max cond(|C|) {cond.max():.1e}, well-posed {wp.mean():.3f}, "
+          f"max err {err[wp].max():.2e} rad", flush=True)
+    assert wp.mean() > 0.8
+    assert err[wp].max() <= PHASE_TOL
+
+
 def test_nodata_pixels_are_invalid_and_ragged_grid(gpu_lib):
     wl = synth.crop("tiny", 37, 43)
     z = synth.make_stack(wl, seed=23)
