@@ -495,6 +495,62 @@ __device__ __forceinline__ void matvec16_lds_steps(const float2* brow, float2 x,
     }
 }
 
+// Four columns of an FP64 Gauss-Jordan step with the pivot-row broadcast
+// folded into v_fmac_f64_dpp (row_newbcast), g[r][j] = fma(-f[r], b, g[r][j])
+// with b = row K's entry j.  Within a block no instruction reads a register
+// written by an earlier one (the row holding row K goes last), so only the
+// leading s_nop is needed for the DPP read hazard.
+template <int R, int NJ, int KS, int KL, int J0>
+__device__ __forceinline__ void gjd_block(double (&g)[R][NJ], const double (&nf)[R]) {
+    constexpr int kNop = J0 == 0 ? 4 : 1;
+    if constexpr (R == 1) {
+        asm volatile(
+        "s_nop %c6\n\t"
+        "v_fmac_f64_dpp %0, %0, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %1, %1, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %2, %2, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %3, %3, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf"
+            : "+v"(g[0][J0]), "+v"(g[0][J0 + 1]), "+v"(g[0][J0 + 2]), "+v"(g[0][J0 + 3])
+            : "v"(nf[0]), "i"(KL), "i"(kNop));
+    } else if constexpr (KS == 0) {
+        asm volatile(
+        "s_nop %c11\n\t"
+        "v_fmac_f64_dpp %1, %0, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %3, %2, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %5, %4, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %7, %6, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, %0, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %2, %2, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %4, %4, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %6, %6, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf"
+            : "+v"(g[0][J0]), "+v"(g[1][J0]), "+v"(g[0][J0 + 1]), "+v"(g[1][J0 + 1]),
+              "+v"(g[0][J0 + 2]), "+v"(g[1][J0 + 2]), "+v"(g[0][J0 + 3]), "+v"(g[1][J0 + 3])
+            : "v"(nf[0]), "v"(nf[1]), "i"(KL), "i"(kNop));
+    } else {
+        asm volatile(
+        "s_nop %c11\n\t"
+        "v_fmac_f64_dpp %0, %1, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %2, %3, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %4, %5, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %6, %7, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %1, %1, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %3, %3, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %5, %5, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %7, %7, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf"
+            : "+v"(g[0][J0]), "+v"(g[1][J0]), "+v"(g[0][J0 + 1]), "+v"(g[1][J0 + 1]),
+              "+v"(g[0][J0 + 2]), "+v"(g[1][J0 + 2]), "+v"(g[0][J0 + 3]), "+v"(g[1][J0 + 3])
+            : "v"(nf[0]), "v"(nf[1]), "i"(KL), "i"(kNop));
+    }
+}
+
+template <int R, int NJ, int KS, int KL, int J0>
+__device__ __forceinline__ void gjd_blocks(double (&g)[R][NJ], const double (&nf)[R]) {
+    if constexpr (J0 < NJ) {
+        gjd_block<R, NJ, KS, KL, J0>(g, nf);
+        gjd_blocks<R, NJ, KS, KL, J0 + 4>(g, nf);
+    }
+}
+
 template <int R, int NJ, int K>
 __device__ __forceinline__ void invert_gr_step(double (&g)[R][NJ], int l, bool& fail, double (&sig)[R]) {
     constexpr int KL = K % 16, KS = K / 16;
@@ -511,11 +567,21 @@ __device__ __forceinline__ void invert_gr_step(double (&g)[R][NJ], int l, bool& 
         f[r] = piv ? 0.0 : g[r][K] * rp;
         g[r][K] = piv ? 1.0 : 0.0;
     }
+    // g[r][j] = fma(-f[r], v, g[r][j]) for every column j, v = row K's entry j
+    if constexpr (R == 2) {
+        double nf[R];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const double v = rowcast<KL>(g[KS][j]);
+        for (int r = 0; r < R; ++r) nf[r] = -f[r];
+        gjd_blocks<R, NJ, KS, KL, 0>(g, nf);
+    } else {
+        // one row per lane: the fused blocks' register constraints cost more
+        // registers (a wavefront per SIMD) than the broadcast moves they save
 #pragma unroll
-        for (int r = 0; r < R; ++r) g[r][j] = fma(-f[r], v, g[r][j]);
+        for (int j = 0; j < NJ; ++j) {
+            const double v = rowcast<KL>(g[KS][j]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) g[r][j] = fma(-f[r], v, g[r][j]);
+        }
     }
 }
 
