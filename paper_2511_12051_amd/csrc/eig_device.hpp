@@ -623,13 +623,97 @@ __device__ __forceinline__ bool factor_c(float2 (&m)[R][NJ], float mu, int N, in
     else return invert_c<NJ>(m[0], mu, N, i, act, rb0, rb1);
 }
 
+// y += M x over four columns with the broadcast of x_j (from lane j % 16)
+// folded into v_fmac_f32_dpp.  Per accumulator the order is that of
+// matvec_r_steps: y.x += (-x_y) m.y then x_x m.x; y.y += x_x m.y then
+// x_y m.x.  The broadcast source x is not written inside the block.
+template <int R, int NJ, int J0>
+__device__ __forceinline__ void matvec_block(const float2 (&m)[R][NJ], const float2 (&x)[R], float2 (&y)[R]) {
+    constexpr int kNop = J0 == 0 ? 4 : 1;
+    constexpr int S = J0 / 16;  // slot of x holding columns J0 .. J0 + 3
+    if constexpr (R == 1) {
+        asm volatile(
+        "s_nop %c16\n\t"
+        "v_fmac_f32_dpp %0, -%3, %5 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %2, %5 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %2, %4 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %3, %4 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%3, %7 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %2, %7 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %2, %6 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %3, %6 row_newbcast:%c13 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%3, %9 row_newbcast:%c14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %2, %9 row_newbcast:%c14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %2, %8 row_newbcast:%c14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %3, %8 row_newbcast:%c14 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%3, %11 row_newbcast:%c15 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %2, %11 row_newbcast:%c15 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %2, %10 row_newbcast:%c15 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %3, %10 row_newbcast:%c15 row_mask:0xf bank_mask:0xf"
+            : "+v"(y[0].x), "+v"(y[0].y)
+            : "v"(x[S].x), "v"(x[S].y), "v"(m[0][J0].x), "v"(m[0][J0].y), "v"(m[0][J0 + 1].x), "v"(m[0][J0 + 1].y),
+              "v"(m[0][J0 + 2].x), "v"(m[0][J0 + 2].y), "v"(m[0][J0 + 3].x), "v"(m[0][J0 + 3].y),
+              "i"(J0 % 16), "i"((J0 + 1) % 16), "i"((J0 + 2) % 16), "i"((J0 + 3) % 16), "i"(kNop));
+    } else {
+        asm volatile(
+        "s_nop %c26\n\t"
+        "v_fmac_f32_dpp %0, -%5, %7 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, -%5, %9 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %7 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %9 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %6 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %8 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %5, %6 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %5, %8 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %11 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, -%5, %13 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %11 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %13 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %10 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %12 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %5, %10 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %5, %12 row_newbcast:%c23 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %15 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, -%5, %17 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %15 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %17 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %14 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %16 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %5, %14 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %5, %16 row_newbcast:%c24 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%5, %19 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, -%5, %21 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %4, %19 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %4, %21 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %4, %18 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %4, %20 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %5, %18 row_newbcast:%c25 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %5, %20 row_newbcast:%c25 row_mask:0xf bank_mask:0xf"
+            : "+v"(y[0].x), "+v"(y[0].y), "+v"(y[1].x), "+v"(y[1].y)
+            : "v"(x[S].x), "v"(x[S].y),
+              "v"(m[0][J0].x), "v"(m[0][J0].y), "v"(m[1][J0].x), "v"(m[1][J0].y),
+              "v"(m[0][J0 + 1].x), "v"(m[0][J0 + 1].y), "v"(m[1][J0 + 1].x), "v"(m[1][J0 + 1].y),
+              "v"(m[0][J0 + 2].x), "v"(m[0][J0 + 2].y), "v"(m[1][J0 + 2].x), "v"(m[1][J0 + 2].y),
+              "v"(m[0][J0 + 3].x), "v"(m[0][J0 + 3].y), "v"(m[1][J0 + 3].x), "v"(m[1][J0 + 3].y),
+              "i"(J0 % 16), "i"((J0 + 1) % 16), "i"((J0 + 2) % 16), "i"((J0 + 3) % 16), "i"(kNop));
+    }
+}
+
+template <int R, int NJ, int J0>
+__device__ __forceinline__ void matvec_blocks(const float2 (&m)[R][NJ], const float2 (&x)[R], float2 (&y)[R]) {
+    if constexpr (J0 < NJ) {
+        matvec_block<R, NJ, J0>(m, x, y);
+        matvec_blocks<R, NJ, J0 + 4>(m, x, y);
+    }
+}
+
 template <int NP, int R, int NJ>
 __device__ __forceinline__ void group_matvec(const float2 (&m)[R][NJ], const float2 (&x)[R], float2 (&y)[R], int i,
                                              float2* xb) {
     if constexpr (NP == 16) {
 #pragma unroll
         for (int r = 0; r < R; ++r) y[r] = make_float2(0.f, 0.f);
-        matvec_r_steps<R, NJ, 0>(m, x, y);
+        matvec_blocks<R, NJ, 0>(m, x, y);  // matvec_r_steps with the broadcasts folded
     } else {
         y[0] = matvec<NJ>(m[0], x[0], i, xb);
     }
