@@ -160,18 +160,30 @@ def kernel_name(stage, wl, prec):
             "link": f"phase_link_kernel<{rows},{cols}>", "compress": "compress_kernel"}[stage]
 
 
+def _code_text(path):
+    """A C++ source with its comments and blank lines removed, so that a
+    comment edit does not count as a kernel change.  (The kernel sources
+    hold no comment markers inside string literals.)"""
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip()).encode()
+
+
 def source_hash(name):
-    """sha256 prefix of a kernel source file together with the package's
-    device headers (the kernels include them), or None if it is missing."""
+    """sha256 prefix of a kernel source file's code together with the
+    package's device headers (the kernels include them), or None if it is
+    missing."""
     import glob
     import hashlib
     csrc = os.path.join(ROOT, "paper_2511_12051_amd", "csrc")
     path = os.path.join(csrc, name)
     if not os.path.exists(path):
         return None
-    h = hashlib.sha256(open(path, "rb").read())
+    h = hashlib.sha256(_code_text(path))
     for hdr in sorted(glob.glob(os.path.join(csrc, "*.hpp"))):
-        h.update(open(hdr, "rb").read())
+        h.update(_code_text(hdr))
     return h.hexdigest()[:16]
 
 

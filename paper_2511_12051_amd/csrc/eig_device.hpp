@@ -1,11 +1,18 @@
 // Device building blocks of the per-pixel eigen-solve shared by the phase
 // linking kernel and its adjoint: group reductions, FP64 and complex FP32
-// Gauss-Jordan inversion with one LDS round trip per step, and shifted
-// inverse iteration for the smallest eigenpair of a Hermitian matrix.
+// Gauss-Jordan inversion, and shifted inverse iteration for the smallest
+// eigenpair of a Hermitian matrix.
 //
-// A group of NP lanes (16 or 32, inside one wavefront) owns one pixel; lane i
-// holds row i, NJ >= N columns.  LDS operations of one wavefront execute in
-// program order, so exchanges within a group need no barrier.
+// A group of NP lanes (inside one wavefront) owns one pixel, NJ >= N
+// columns per row.  Two forms:
+//  - 16 lanes (one DPP row), R = 1 or 2 rows per lane (rows l, l + 16): the
+//    pivot row of a step and the iterate of a mat-vec are broadcast by DPP
+//    row_newbcast, folded into the FMAs; no LDS traffic.  The linking kernel
+//    uses it for every N, the adjoint for N <= 16.
+//  - 32 lanes, one row per lane (the adjoint for N > 16): exchanges through a
+//    few hundred bytes of LDS per group, one round trip per step.  LDS
+//    operations of one wavefront execute in program order, so exchanges
+//    within a group need no barrier.
 #pragma once
 #include <cmath>
 
