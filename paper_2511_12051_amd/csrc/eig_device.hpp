@@ -574,22 +574,14 @@ __device__ __forceinline__ void invert_gr_step(double (&g)[R][NJ], int l, bool& 
         f[r] = piv ? 0.0 : g[r][K] * rp;
         g[r][K] = piv ? 1.0 : 0.0;
     }
-    // g[r][j] = fma(-f[r], v, g[r][j]) for every column j, v = row K's entry j
-    if constexpr (R == 2) {
-        double nf[R];
+    // g[r][j] = fma(-f[r], v, g[r][j]) for every column j, v = row K's entry j.
+    // (With one row per lane the blocks' register constraints cost a
+    // wavefront per SIMD, and the saved broadcast moves still win: the
+    // kernel is bound by instruction issue.)
+    double nf[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) nf[r] = -f[r];
-        gjd_blocks<R, NJ, KS, KL, 0>(g, nf);
-    } else {
-        // one row per lane: the fused blocks' register constraints cost more
-        // registers (a wavefront per SIMD) than the broadcast moves they save
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const double v = rowcast<KL>(g[KS][j]);
-#pragma unroll
-            for (int r = 0; r < R; ++r) g[r][j] = fma(-f[r], v, g[r][j]);
-        }
-    }
+    for (int r = 0; r < R; ++r) nf[r] = -f[r];
+    gjd_blocks<R, NJ, KS, KL, 0>(g, nf);
 }
 
 template <int R, int NJ, int K>
