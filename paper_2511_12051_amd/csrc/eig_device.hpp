@@ -32,14 +32,10 @@ __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
 }
 
-// An opaque copy of a pointer: loads through it are neither merged with
-// earlier loads of the same address nor hoisted above this point (out of a
-// loop), which would keep the loaded values live in registers.
-template <class T>
-__device__ __forceinline__ T* opaque(T* p) {
-    asm volatile("" : "+v"(p));
-    return p;
-}
+// Opaque copies of an integer: offsets formed from them are neither merged
+// with earlier ones nor hoisted above this point (out of a loop), so loads
+// through them are not hoisted either (which would keep the loaded values
+// live in registers).
 __device__ __forceinline__ int opaque_int(int v) {
     asm volatile("" : "+v"(v));
     return v;
@@ -476,19 +472,6 @@ __device__ __forceinline__ bool invert_cr(float2 (&m)[R][NJ], float mu, int N, i
     return pd;
 }
 
-// y += M x over columns J onwards, x_j broadcast from its owner lane
-template <int R, int NJ, int J>
-__device__ __forceinline__ void matvec_r_steps(const float2 (&m)[R][NJ], const float2 (&x)[R], float2 (&y)[R]) {
-    if constexpr (J < NJ) {
-        const float vx = rowcast<J % 16>(x[J / 16].x), vy = rowcast<J % 16>(x[J / 16].y);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            y[r].x = fmaf(m[r][J].x, vx, fmaf(-m[r][J].y, vy, y[r].x));
-            y[r].y = fmaf(m[r][J].x, vy, fmaf(m[r][J].y, vx, y[r].y));
-        }
-        matvec_r_steps<R, NJ, J + 1>(m, x, y);
-    }
-}
 
 // y += B x over columns J onwards, B's row in LDS element-major (one row per lane)
 template <int NJ, int J>
@@ -623,9 +606,10 @@ __device__ __forceinline__ bool factor_c(float2 (&m)[R][NJ], float mu, int N, in
 }
 
 // y += M x over four columns with the broadcast of x_j (from lane j % 16)
-// folded into v_fmac_f32_dpp.  Per accumulator the order is that of
-// matvec_r_steps: y.x += (-x_y) m.y then x_x m.x; y.y += x_x m.y then
-// x_y m.x.  The broadcast source x is not written inside the block.
+// folded into v_fmac_f32_dpp.  Columns in order, and per column and
+// accumulator: y.x = fma(m.x, x_x, fma(-m.y, x_y, y.x)) and
+// y.y = fma(m.x, x_y, fma(m.y, x_x, y.y)).  The broadcast source x is not
+// written inside the block.
 template <int R, int NJ, int J0>
 __device__ __forceinline__ void matvec_block(const float2 (&m)[R][NJ], const float2 (&x)[R], float2 (&y)[R]) {
     constexpr int kNop = J0 == 0 ? 4 : 1;
@@ -712,7 +696,7 @@ __device__ __forceinline__ void group_matvec(const float2 (&m)[R][NJ], const flo
     if constexpr (NP == 16) {
 #pragma unroll
         for (int r = 0; r < R; ++r) y[r] = make_float2(0.f, 0.f);
-        matvec_blocks<R, NJ, 0>(m, x, y);  // matvec_r_steps with the broadcasts folded
+        matvec_blocks<R, NJ, 0>(m, x, y);
     } else {
         y[0] = matvec<NJ>(m[0], x[0], i, xb);
     }
