@@ -268,134 +268,133 @@ __device__ __forceinline__ double rowcast(double v) {
 // 1/p itself; the owner keeps row K as S_K with the diagonal slot set to 1,
 // every other row i of an active group subtracts (S_i[K] / p) S_K.
 // Four columns of a complex Gauss-Jordan step with the pivot-row broadcast
-// folded into the FMAs (v_fmac_f32_dpp with row_newbcast:KL), so no separate
-// broadcast moves are issued.  The compiler does not fold a broadcast into an
-// FMA by itself.  Per entry the operations and their order are those of
-// invert_cr_step's reference loop: x += r_y fy, then x += r_x (-fx); y +=
-// r_x (-fy), then y += r_y (-fx), each a single-rounding FMA.  The four
+// folded into the FMAs (v_fmac_f32_dpp with row_newbcast:KL; negated terms
+// use the instruction's negate modifier on the broadcast operand), so no
+// separate broadcast or negation instructions are issued.  The compiler does
+// not fold a broadcast into an FMA by itself.  Per entry (r_x, r_y = row K's
+// entry): x = fma(-fx, r_x, fma(fy, r_y, x)) and
+// y = fma(-fx, r_y, fma(-fy, r_x, y)), each a single-rounding FMA.  The four
 // phases are ordered so that no broadcast read follows a write of the same
 // register within two instructions (the DPP read hazard); the leading s_nop
 // covers writes by the code just before the block.  Only the pivot lane's
 // value is ever broadcast, and its row is left unchanged (its multipliers
 // are zero).
 template <int R, int NJ, int KS, int KL, int J0>
-__device__ __forceinline__ void gj_block(float2 (&m)[R][NJ], const float (&fy)[R], const float (&nfy)[R],
-                                         const float (&nfx)[R]) {
+__device__ __forceinline__ void gj_block(float2 (&m)[R][NJ], const float (&fy)[R], const float (&fx)[R]) {
     // wait states before the first DPP read: 2 cover a VALU write just
     // before the block; the first block of a step may follow a block
     // boundary and gets 5, which also covers a write of EXEC
     constexpr int kNop = J0 == 0 ? 4 : 1;
     if constexpr (R == 1) {
         asm volatile(
-        "s_nop %c12\n\t"
-        "v_fmac_f32_dpp %0, %1, %8 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %3, %8 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %4, %5, %8 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %6, %7, %8 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %0, %9 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %2, %9 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %5, %4, %9 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %7, %6, %9 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %0, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %2, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %4, %4, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %6, %6, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %1, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %3, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %5, %5, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %7, %7, %10 row_newbcast:%c11 row_mask:0xf bank_mask:0xf"
+        "s_nop %c11\n\t"
+        "v_fmac_f32_dpp %0, %1, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %3, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %5, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, %7, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, -%0, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, -%2, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, -%4, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, -%6, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%0, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, -%2, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, -%4, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, -%6, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, -%1, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, -%3, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, -%5, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, -%7, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf"
             : "+v"(m[0][J0].x), "+v"(m[0][J0].y), "+v"(m[0][J0 + 1].x), "+v"(m[0][J0 + 1].y),
               "+v"(m[0][J0 + 2].x), "+v"(m[0][J0 + 2].y), "+v"(m[0][J0 + 3].x), "+v"(m[0][J0 + 3].y)
-            : "v"(fy[0]), "v"(nfy[0]), "v"(nfx[0]), "i"(KL), "i"(kNop));
+            : "v"(fy[0]), "v"(fx[0]), "i"(KL), "i"(kNop));
     } else if constexpr (KS == 0) {
         asm volatile(
-        "s_nop %c23\n\t"
-        "v_fmac_f32_dpp %2, %1, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %6, %5, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %10, %9, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %14, %13, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %1, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %4, %5, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %8, %9, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %12, %13, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %0, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %7, %4, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %11, %8, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %15, %12, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %0, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %5, %4, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %9, %8, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %13, %12, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %0, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %6, %4, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %10, %8, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %14, %12, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %0, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %4, %4, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %8, %8, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %12, %12, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %1, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %7, %5, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %11, %9, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %15, %13, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %1, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %5, %5, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %9, %9, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %13, %13, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf"
+        "s_nop %c21\n\t"
+        "v_fmac_f32_dpp %2, %1, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, %5, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %10, %9, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %14, %13, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, %1, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %5, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %8, %9, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %12, %13, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, -%0, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, -%4, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %11, -%8, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %15, -%12, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, -%0, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, -%4, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %9, -%8, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %13, -%12, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, -%0, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, -%4, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %10, -%8, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %14, -%12, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%0, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, -%4, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %8, -%8, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %12, -%12, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, -%1, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, -%5, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %11, -%9, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %15, -%13, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, -%1, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, -%5, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %9, -%9, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %13, -%13, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf"
             : "+v"(m[0][J0].x), "+v"(m[0][J0].y), "+v"(m[1][J0].x), "+v"(m[1][J0].y),
               "+v"(m[0][J0 + 1].x), "+v"(m[0][J0 + 1].y), "+v"(m[1][J0 + 1].x), "+v"(m[1][J0 + 1].y),
               "+v"(m[0][J0 + 2].x), "+v"(m[0][J0 + 2].y), "+v"(m[1][J0 + 2].x), "+v"(m[1][J0 + 2].y),
               "+v"(m[0][J0 + 3].x), "+v"(m[0][J0 + 3].y), "+v"(m[1][J0 + 3].x), "+v"(m[1][J0 + 3].y)
-            : "v"(fy[0]), "v"(nfy[0]), "v"(nfx[0]), "v"(fy[1]), "v"(nfy[1]), "v"(nfx[1]), "i"(KL), "i"(kNop));
+            : "v"(fy[0]), "v"(fx[0]), "v"(fy[1]), "v"(fx[1]), "i"(KL), "i"(kNop));
     } else {
         asm volatile(
-        "s_nop %c23\n\t"
-        "v_fmac_f32_dpp %0, %3, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %4, %7, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %8, %11, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %12, %15, %16 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %3, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %6, %7, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %10, %11, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %14, %15, %19 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %2, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %5, %6, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %9, %10, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %13, %14, %17 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %2, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %7, %6, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %11, %10, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %15, %14, %20 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %0, %2, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %4, %6, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %8, %10, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %12, %14, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %2, %2, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %6, %6, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %10, %10, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %14, %14, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %1, %3, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %5, %7, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %9, %11, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %13, %15, %18 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %3, %3, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %7, %7, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %11, %11, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f32_dpp %15, %15, %21 row_newbcast:%c22 row_mask:0xf bank_mask:0xf"
+        "s_nop %c21\n\t"
+        "v_fmac_f32_dpp %0, %3, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %7, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %8, %11, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %12, %15, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %3, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, %7, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %10, %11, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %14, %15, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, -%2, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, -%6, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %9, -%10, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %13, -%14, %16 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, -%2, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, -%6, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %11, -%10, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %15, -%14, %18 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %0, -%2, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, -%6, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %8, -%10, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %12, -%14, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, -%2, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, -%6, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %10, -%10, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %14, -%14, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, -%3, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, -%7, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %9, -%11, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %13, -%15, %17 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, -%3, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, -%7, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %11, -%11, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %15, -%15, %19 row_newbcast:%c20 row_mask:0xf bank_mask:0xf"
             : "+v"(m[0][J0].x), "+v"(m[0][J0].y), "+v"(m[1][J0].x), "+v"(m[1][J0].y),
               "+v"(m[0][J0 + 1].x), "+v"(m[0][J0 + 1].y), "+v"(m[1][J0 + 1].x), "+v"(m[1][J0 + 1].y),
               "+v"(m[0][J0 + 2].x), "+v"(m[0][J0 + 2].y), "+v"(m[1][J0 + 2].x), "+v"(m[1][J0 + 2].y),
               "+v"(m[0][J0 + 3].x), "+v"(m[0][J0 + 3].y), "+v"(m[1][J0 + 3].x), "+v"(m[1][J0 + 3].y)
-            : "v"(fy[0]), "v"(nfy[0]), "v"(nfx[0]), "v"(fy[1]), "v"(nfy[1]), "v"(nfx[1]), "i"(KL), "i"(kNop));
+            : "v"(fy[0]), "v"(fx[0]), "v"(fy[1]), "v"(fx[1]), "i"(KL), "i"(kNop));
     }
 }
 
 template <int R, int NJ, int KS, int KL, int J0>
-__device__ __forceinline__ void gj_blocks(float2 (&m)[R][NJ], const float (&fy)[R], const float (&nfy)[R],
-                                          const float (&nfx)[R]) {
+__device__ __forceinline__ void gj_blocks(float2 (&m)[R][NJ], const float (&fy)[R], const float (&fx)[R]) {
     if constexpr (J0 < NJ) {
-        gj_block<R, NJ, KS, KL, J0>(m, fy, nfy, nfx);
-        gj_blocks<R, NJ, KS, KL, J0 + 4>(m, fy, nfy, nfx);
+        gj_block<R, NJ, KS, KL, J0>(m, fy, fx);
+        gj_blocks<R, NJ, KS, KL, J0 + 4>(m, fy, fx);
     }
 }
 
@@ -421,16 +420,10 @@ __device__ __forceinline__ void invert_cr_step(float2 (&m)[R][NJ], float mu, int
         m[r][K] = make_float2(piv ? 1.f : 0.f, 0.f);
     }
     static_assert(NJ % 4 == 0, "columns in blocks of four");
-    float nfx[R], nfy[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        nfx[r] = -fx[r];
-        nfy[r] = -fy[r];
-    }
     // for every column j and row r, with (r_x, r_y) = row K's entry j:
     //   m[r][j].x = fma(-fx, r_x, fma(fy, r_y, m[r][j].x))
     //   m[r][j].y = fma(-fx, r_y, fma(-fy, r_x, m[r][j].y))
-    gj_blocks<R, NJ, KS, KL, 0>(m, fy, nfy, nfx);
+    gj_blocks<R, NJ, KS, KL, 0>(m, fy, fx);
 }
 
 // Smallest N served by the NJ-column kernels (NJ = 12 serves every N up to
@@ -486,58 +479,58 @@ __device__ __forceinline__ void matvec16_lds_steps(const float2* brow, float2 x,
 }
 
 // Four columns of an FP64 Gauss-Jordan step with the pivot-row broadcast
-// folded into v_fmac_f64_dpp (row_newbcast), g[r][j] = fma(-f[r], b, g[r][j])
-// with b = row K's entry j.  Within a block no instruction reads a register
+// folded into v_fmac_f64_dpp (row_newbcast, negate modifier on the broadcast
+// operand), g[r][j] = fma(-f[r], b, g[r][j]) with b = row K's entry j.  Within a block no instruction reads a register
 // written by an earlier one (the row holding row K goes last), so only the
 // leading s_nop is needed for the DPP read hazard.
 template <int R, int NJ, int KS, int KL, int J0>
-__device__ __forceinline__ void gjd_block(double (&g)[R][NJ], const double (&nf)[R]) {
+__device__ __forceinline__ void gjd_block(double (&g)[R][NJ], const double (&f)[R]) {
     constexpr int kNop = J0 == 0 ? 4 : 1;
     if constexpr (R == 1) {
         asm volatile(
         "s_nop %c6\n\t"
-        "v_fmac_f64_dpp %0, %0, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %1, %1, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %2, %2, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %3, %3, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf"
+        "v_fmac_f64_dpp %0, -%0, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %1, -%1, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %2, -%2, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %3, -%3, %4 row_newbcast:%c5 row_mask:0xf bank_mask:0xf"
             : "+v"(g[0][J0]), "+v"(g[0][J0 + 1]), "+v"(g[0][J0 + 2]), "+v"(g[0][J0 + 3])
-            : "v"(nf[0]), "i"(KL), "i"(kNop));
+            : "v"(f[0]), "i"(KL), "i"(kNop));
     } else if constexpr (KS == 0) {
         asm volatile(
         "s_nop %c11\n\t"
-        "v_fmac_f64_dpp %1, %0, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %3, %2, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %5, %4, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %7, %6, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %0, %0, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %2, %2, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %4, %4, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %6, %6, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf"
+        "v_fmac_f64_dpp %1, -%0, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %3, -%2, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %5, -%4, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %7, -%6, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %0, -%0, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %2, -%2, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %4, -%4, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %6, -%6, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf"
             : "+v"(g[0][J0]), "+v"(g[1][J0]), "+v"(g[0][J0 + 1]), "+v"(g[1][J0 + 1]),
               "+v"(g[0][J0 + 2]), "+v"(g[1][J0 + 2]), "+v"(g[0][J0 + 3]), "+v"(g[1][J0 + 3])
-            : "v"(nf[0]), "v"(nf[1]), "i"(KL), "i"(kNop));
+            : "v"(f[0]), "v"(f[1]), "i"(KL), "i"(kNop));
     } else {
         asm volatile(
         "s_nop %c11\n\t"
-        "v_fmac_f64_dpp %0, %1, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %2, %3, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %4, %5, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %6, %7, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %1, %1, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %3, %3, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %5, %5, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
-        "v_fmac_f64_dpp %7, %7, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf"
+        "v_fmac_f64_dpp %0, -%1, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %2, -%3, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %4, -%5, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %6, -%7, %8 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %1, -%1, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %3, -%3, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %5, -%5, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f64_dpp %7, -%7, %9 row_newbcast:%c10 row_mask:0xf bank_mask:0xf"
             : "+v"(g[0][J0]), "+v"(g[1][J0]), "+v"(g[0][J0 + 1]), "+v"(g[1][J0 + 1]),
               "+v"(g[0][J0 + 2]), "+v"(g[1][J0 + 2]), "+v"(g[0][J0 + 3]), "+v"(g[1][J0 + 3])
-            : "v"(nf[0]), "v"(nf[1]), "i"(KL), "i"(kNop));
+            : "v"(f[0]), "v"(f[1]), "i"(KL), "i"(kNop));
     }
 }
 
 template <int R, int NJ, int KS, int KL, int J0>
-__device__ __forceinline__ void gjd_blocks(double (&g)[R][NJ], const double (&nf)[R]) {
+__device__ __forceinline__ void gjd_blocks(double (&g)[R][NJ], const double (&f)[R]) {
     if constexpr (J0 < NJ) {
-        gjd_block<R, NJ, KS, KL, J0>(g, nf);
-        gjd_blocks<R, NJ, KS, KL, J0 + 4>(g, nf);
+        gjd_block<R, NJ, KS, KL, J0>(g, f);
+        gjd_blocks<R, NJ, KS, KL, J0 + 4>(g, f);
     }
 }
 
@@ -561,10 +554,7 @@ __device__ __forceinline__ void invert_gr_step(double (&g)[R][NJ], int l, bool& 
     // (With one row per lane the blocks' register constraints cost a
     // wavefront per SIMD, and the saved broadcast moves still win: the
     // kernel is bound by instruction issue.)
-    double nf[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) nf[r] = -f[r];
-    gjd_blocks<R, NJ, KS, KL, 0>(g, nf);
+    gjd_blocks<R, NJ, KS, KL, 0>(g, f);
 }
 
 template <int R, int NJ, int K>
