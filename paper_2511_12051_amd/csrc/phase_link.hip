@@ -282,7 +282,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     }
 }
 
-// Groups with two rows per lane (N > 16) run persistently: the grid (a few
+// Groups with two rows per lane (N > 16) run persistently: the grid (16
 // times the resident workgroups) strides over the pixel blocks, which avoids
 // dispatching hundreds of thousands of short workgroups; one-row groups keep
 // one block per workgroup.  Two-row kernels are held to two wavefronts per
@@ -336,7 +336,7 @@ pl_status launch_persistent(const LinkArgs& a, int64_t blocks, hipStream_t s) {
         cus[dev] = c;
         per_cu[dev] = n;
     }
-    int64_t grid = R == 1 ? blocks : (int64_t)per_cu[dev] * cus[dev] * 4;
+    int64_t grid = R == 1 ? blocks : (int64_t)per_cu[dev] * cus[dev] * 16;  // 16: measured best of 2, 4, 8, 16
     if (grid > blocks) grid = blocks;
     if (grid > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link: too many pixels");
     if (grid < 1) grid = 1;
