@@ -135,12 +135,16 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     }
     const Tri tri{lds + wave * Tri::WAVE_ENTRIES, grp, l, N};
     if constexpr (R == 2) {
-        // C's upper triangle goes to LDS now; B is formed there after step 1
+        // C's upper triangle goes to LDS now; B is formed there after step 1.
+        // The fence orders these stores after the previous pixel's reads of
+        // the triangle by other lanes (persistent loop).
+        wave_sync();
         const int ub[2] = {tri.up_base(l, 0), tri.up_base(l, 1)};
         [&]<int... J>(std::integer_sequence<int, J...>) {
 #pragma unroll
             for (int r = 0; r < R; ++r) ((tri.w[tri.template own<J>(ub[r], l, r, N)] = c[r][J]), ...);
         }(std::make_integer_sequence<int, NJ>{});
+        wave_sync();
     }
     // ---- 1. FP64 inverse of G = |C|
     bool use_evd = a.method == PL_LINK_EVD;
@@ -199,6 +203,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
             };
             (four(std::integral_constant<int, J>{}), ...);
         }(std::make_integer_sequence<int, NJ>{});
+        wave_sync();  // B's triangle is read across lanes from here on
     }
     float mu = 0.99f;
     if (gany<64>(use_evd, 0)) {

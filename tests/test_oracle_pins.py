@@ -304,6 +304,67 @@ def test_phase_screen_shifts_linked_phase_exactly():
     assert np.abs(diff).max() < 1e-9
 
 
+def _random_abs_coherence(rng, N, looks):
+    z = rng.normal(size=(N, looks)) + 1j * rng.normal(size=(N, looks))
+    z[1:] += rng.uniform(0.2, 1.5) * z[:1]
+    A = z @ z.conj().T
+    d = np.sqrt(np.real(np.diag(A)))
+    return np.abs(A / np.outer(d, d))
+
+
+@pytest.mark.parametrize("N", [3, 4, 7, 12, 16, 20, 25, 32])
+def test_ldl_pivots_are_squared_cholesky_diagonal(N):
+    """The unpivoted LDL^T pivots of an SPD matrix are the squares of its
+    Cholesky diagonal (LAPACK) and the ratios of consecutive leading principal
+    minors; their product is det G."""
+    rng = np.random.default_rng(100 + N)
+    G = np.stack([_random_abs_coherence(rng, N, 3 * N + k) for k in range(6)])
+    d = O.ldl_pivots(G)
+    L = np.linalg.cholesky(G)
+    np.testing.assert_allclose(d, np.einsum("pii->pi", L) ** 2, rtol=1e-10)
+    for p in range(len(G)):
+        minors = np.array([np.linalg.det(G[p, :k, :k]) for k in range(1, N + 1)])
+        np.testing.assert_allclose(d[p], minors / np.concatenate([[1.0], minors[:-1]]), rtol=1e-8)
+        np.testing.assert_allclose(np.prod(d[p]), np.linalg.det(G[p]), rtol=1e-8)
+
+
+def _unit_diag_from_ldl(Lstrict, d0_target, k):
+    """A unit-diagonal SPD matrix G = L D L^T with nonnegative entries whose
+    LDL^T pivot number k is d0_target: every pivot is 1 - sum_j L_ij^2 d_j."""
+    N = Lstrict.shape[0]
+    L = np.eye(N) + np.tril(Lstrict, -1)
+    d = np.zeros(N)
+    for i in range(N):
+        if i == k:
+            # rescale row k's multipliers so that its pivot is the target
+            s = np.sum(L[i, :i] ** 2 * d[:i])
+            L[i, :i] *= np.sqrt((1.0 - d0_target) / s)
+        d[i] = 1.0 - np.sum(L[i, :i] ** 2 * d[:i])
+        assert d[i] > 0
+    return L @ np.diag(d) @ L.T, d
+
+
+@pytest.mark.parametrize("k", [2, 5, 9])
+def test_fallback_decided_by_a_deep_pivot(k):
+    """A pivot at index k >= 2 just below / above tau switches EMI to EVD;
+    built from a prescribed LDL^T so that the pivot is known exactly."""
+    rng = np.random.default_rng(200 + k)
+    N = 12
+    Ls = rng.uniform(0.0, 0.25, (N, N))
+    phi = rng.uniform(-np.pi, np.pi, N)
+    for target, want in ((0.5 * O.TAU_PIVOT, O.FLAG_EVD), (2.0 * O.TAU_PIVOT, O.FLAG_EMI)):
+        G, d = _unit_diag_from_ldl(Ls, target, k)
+        np.testing.assert_allclose(np.diag(G), 1.0, atol=1e-14)
+        assert np.all(np.delete(d, k) > 1e-3)  # only pivot k is small
+        np.testing.assert_allclose(O.ldl_pivots(G[None])[0], d, rtol=1e-7, atol=1e-12)
+        Cm = np.exp(1j * phi)[:, None] * G * np.exp(-1j * phi)[None, :]
+        out = O.phase_link(Cm[None], ref=0)
+        assert out["flag"][0] == want, (k, target)
+        assert abs(out["min_pivot"][0] - target) < 1e-3 * target
+        # noise-free model: either branch recovers the phases exactly
+        assert np.abs(O.wrap(out["phase"][:, 0] - (phi - phi[0]))).max() < 1e-6
+
+
 def test_fallback_rule_rank_one_is_evd_and_exact():
     N = 6
     phi = np.linspace(-3, 3, N)
@@ -386,6 +447,48 @@ def test_sequential_is_append_only():
     for x, y in zip(a2, a3[:2]):
         np.testing.assert_array_equal(x["phasor"], y["phasor"])
         np.testing.assert_array_equal(x["kappa"], y["kappa"])
+
+
+def test_sequential_statistics_window_and_n_eff():
+    """Mini-stack k merges the amplitude statistics of mini-stacks k-K..k with
+    n_eff = (K+1) M (reading R8).  Amplitudes are constant within each
+    mini-stack, so the pooled Rayleigh scale of a pixel is half the mean of
+    its squared amplitudes over the merged mini-stacks and every GLRT decision
+    below follows from T = 2 n ln((s_p+s_q)^2 / (4 s_p s_q)) by hand:
+
+      q1: amplitude 1.6 throughout: scale ratio 2.56, T = 0.4265 n: an SHP for
+          n = 15 (6.4) and not for n >= 30 (12.8, 19.2)
+      q2: amplitude 3 in mini-stack 0 only, then 1: at k = 3 (window 1..3)
+          ratio 1 -> SHP; a window reaching back to 0 gives ratio 3 -> not
+      q3: amplitude 2 in mini-stacks 1, 2, 1 in 3: window 1..3 ratio 3,
+          T(45) = 25.9 -> not; the current mini-stack alone: ratio 1 -> SHP
+      q4: amplitude 1 in 0..2, 3 in 3: window 1..3 ratio 11/3,
+          T(45) = 35.6 -> not; mini-stacks 1..2 alone: ratio 1 -> SHP
+    The centre pixel p has amplitude 1 throughout."""
+    M, K, T = 15, 2, 4
+    rng = np.random.default_rng(15)
+    amp = np.ones((T, 3, 3))
+    q1, q2, q3, q4 = (0, 0), (0, 2), (2, 0), (2, 2)  # window bits 0, 2, 6, 8
+    amp[:, q1[0], q1[1]] = 1.6
+    amp[0, q2[0], q2[1]] = 3.0
+    amp[1:3, q3[0], q3[1]] = 2.0
+    amp[3, q4[0], q4[1]] = 3.0
+    batches = [amp[k][None] * np.exp(1j * rng.uniform(-np.pi, np.pi, (M, 3, 3))) for k in range(T)]
+    out = O.sequential(batches, K, (1, 1, 3, 3), 1e-3)
+    bits = [O.mask_bits(o["mask"], (1, 1, 3, 3))[0, 0] for o in out]
+    # mini-stack 0: n = 15, window {0}
+    assert bits[0][0] and not bits[0][2]  # q1 SHP at n = 15; q2: ratio 9 -> not
+    # mini-stack 3: n = 45, window {1, 2, 3}
+    assert not bits[3][0]
+    assert bits[3][2]
+    assert not bits[3][6]
+    assert not bits[3][8]
+    assert bits[3][4]  # the centre itself
+    # the hand-computed statistics behind the decisions
+    thr = O.glrt_threshold(1e-3)
+    t = lambda r, n: 2 * n * math.log((1 + r) ** 2 / (4 * r))
+    assert t(2.56, 15) < thr < t(2.56, 30)
+    assert t(3.0, 45) > thr and t(11 / 3, 45) > thr and t(9.0, 15) > thr
 
 
 # ---------------------------------------------------------------- adjoint
