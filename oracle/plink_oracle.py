@@ -46,6 +46,8 @@ Readings taken where the paper is silent (each one is listed in the design doc):
   are those of mini-stacks k-K..k (the ones behind the retained compressed
   SLCs plus the current one), each weighted by its number of images
   (eq. merged-mean / merged-variance, "evenly weight the previous n images").
+* R18 exponential weights: the group of age a is weighted by M decay^a and
+  the GLRT sample count is the sum of the weights (decay = 1: reading R8).
 """
 from __future__ import annotations
 
@@ -485,31 +487,43 @@ def link_ministack(stack, first_real, window, alpha, ref, n_eff=None,
             "coh": Cm, "valid": valid, "link": pl, "phasor": ph, "kappa": kappa}
 
 
-def sequential(batches, K, window, alpha, method="emi"):
+def sequential(batches, K, window, alpha, method="emi", reference="compressed", decay=1.0):
     """Mini-stack reference scheme of Sec. 2.2 (Fig. 1): mini-stack k is
     [kappa_{k-K} .. kappa_{k-1} | M new SLCs]; its reference is the most
     recent compressed SLC (index 0 for the first mini-stack); earlier batches
     are never re-estimated.  Returns per mini-stack the phasors of its real
-    SLCs and its compressed SLC."""
+    SLCs and its compressed SLC.
+
+    reference="last" forms each compressed SLC with the phasors re-referenced
+    to the last real SLC of its mini-stack, so the next mini-stack is linked
+    relative to that date (supplement, "Compressed SLC strategy for separate
+    batched processing").  decay < 1 weights the statistics of the mini-stack
+    of age a (0 = the current one) by M decay^a instead of M (Sec. 3.1: an
+    exponential decay that prioritises recent observations), and n_eff is the
+    sum of the weights (reading R18)."""
     kappas, groups, out = [], [], []
     for k, znew in enumerate(batches):
         znew = np.asarray(znew)
         M = znew.shape[0]
         groups.append(amplitude_stats(znew) + (M,))
         keep = groups[-(K + 1):]
-        mean, var = merge_amplitude_stats([g[0] for g in keep], [g[1] for g in keep],
-                                          [g[2] for g in keep])
-        n_eff = float(sum(g[2] for g in keep))
+        wts = [g[2] * decay ** (len(keep) - 1 - j) for j, g in enumerate(keep)]
+        mean, var = merge_amplitude_stats([g[0] for g in keep], [g[1] for g in keep], wts)
+        n_eff = float(sum(wts))
         comp = kappas[-K:] if K > 0 else []
         stack = np.concatenate([np.stack(comp)] + [znew]) if comp else znew
         ref = len(comp) - 1 if comp else 0
         res = link_ministack(stack, len(comp), window, alpha, ref, n_eff=n_eff,
                              stats=(mean, var), method=method)
-        kappas.append(res["kappa"])
-        out.append({"phasor": res["phasor"][len(comp):], "kappa": res["kappa"],
-                    "n_comp": len(comp), "ref": ref, "mask": res["mask"],
+        kappa = res["kappa"]
+        if reference == "last":
+            rot = res["phasor"] * np.conj(res["phasor"][-1])[None]
+            kappa = compress(stack, len(comp), rot, window)
+        kappas.append(kappa)
+        out.append({"phasor": res["phasor"][len(comp):], "kappa": kappa,
+                    "n_comp": len(comp), "ref": ref, "mask": res["mask"], "n_eff": n_eff,
                     "flag": res["link"]["flag"], "cond": res["link"]["cond"],
-                    "coh": res["coh"]})
+                    "coh": res["coh"], "mean": mean, "var": var})
     return out
 
 

@@ -10,8 +10,10 @@ is not resolvable.
 Tolerance.  The gradient is a sum over the window of S_p z_q; on well-posed
 pixels the FP32 forward resolves the phases to <= 1e-3 rad, and the adjoint's
 relative error is bounded by the same rounding amplified by one more factor of
-the eigen-gap.  The test asks for 1e-3 of the largest gradient magnitude per
-element, and 1e-2 relative on every element above a tenth of it.
+the eigen-gap.  The bars sit at about twice the largest error measured on
+these cases: 3e-4 of the largest gradient magnitude per element, and 5e-3
+relative on every element above a tenth of it.  The well-posed set is the
+forward tests' (tests/phase_parity.py), from the oracle alone.
 """
 import numpy as np
 import pytest
@@ -19,14 +21,12 @@ import torch
 
 import synth
 from oracle import plink_oracle as O
+from phase_parity import well_posed, sensitivity
 
 pytestmark = pytest.mark.gpu
 
-PHASE_TOL = 1e-3
-EPS_FLOOR = 1e-6
-SAFETY = 3.0
-ABS_TOL = 1e-3   # of max |grad|
-REL_TOL = 1e-2   # on elements above 0.1 max |grad|
+ABS_TOL = 3e-4   # of max |grad|
+REL_TOL = 5e-3   # on elements above 0.1 max |grad|
 
 
 def _forward(plink, z, wl, ref, method, prec="fp32"):
@@ -38,10 +38,7 @@ def _forward(plink, z, wl, ref, method, prec="fp32"):
 
 
 def _well_posed(Cgpu, Corc, ref, method):
-    sens = O.phase_sensitivity(Corc, ref=ref, method=method)
-    dC = np.abs(Cgpu.astype(np.complex128) - Corc).reshape(len(sens), -1)
-    eps = np.maximum(np.nanmax(np.where(np.isfinite(dC), dC, np.inf), axis=1), EPS_FLOOR)
-    return SAFETY * sens * eps <= PHASE_TOL
+    return well_posed(sensitivity(Corc, ref, method), "fp32")
 
 
 def _compare(g_gpu, g_orc, what):

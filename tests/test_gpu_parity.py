@@ -3,12 +3,11 @@ element, on seeded synthetic stacks that span several tiles with ragged
 edges, plus edge cases.
 
 Tolerances (from the workload descriptions): SHP masks bit-exact except GLRT
-tests within 1e-9 of the threshold; coherence within 1e-4 per element; linked
-phases within 1e-3 rad (wrapped) on well-posed pixels.  A pixel is well-posed
-when the oracle's statistical phase sensitivity (rad per unit change of C)
-times the coherence difference actually present at that pixel (at least
-1e-6, the FP32 floor of the eigen-solver), times a safety factor of 3, stays
-below 1e-3 rad; the others are counted and must be a small minority.
+tests within 1e-9 of the threshold; coherence within 1e-4 per element (and
+within the fixed per-precision bound EPS that the phase criterion assumes);
+linked phases within 1e-3 rad (wrapped) on the pixels the oracle alone
+marks well posed, and within a per-pixel error bound everywhere else
+(tests/phase_parity.py states the criterion).
 """
 import numpy as np
 import pytest
@@ -16,13 +15,9 @@ import torch
 
 import synth
 from oracle import plink_oracle as O
+from phase_parity import COH_TOL, EPS, PHASE_TOL, check_phases, coherence_error, phase_errors, sensitivity
 
 pytestmark = pytest.mark.gpu
-
-PHASE_TOL = 1e-3
-COH_TOL = 1e-4
-EPS_FLOOR = 1e-6
-SAFETY = 3.0
 
 
 def _wl(name, R=None, C=None):
@@ -51,7 +46,7 @@ class Case:
         self.orc = O.link_ministack(self.z, self.first_real, wl.window, wl.alpha, self.ref)
         _, _, _, self.stat = O.shp_select(self.orc["mean"], self.orc["var"], wl.n_new, wl.window,
                                           wl.alpha, return_stat=True)
-        self.sens = O.phase_sensitivity(self.orc["coh"], ref=self.ref)
+        self.sens = sensitivity(self.orc["coh"], self.ref)
 
 
 _cache = {}
@@ -79,16 +74,6 @@ def gpu_path(plink, c: Case, prec="fp32"):
                 mask=mask.cpu().numpy().view(np.uint32), count=count.cpu().numpy().view(np.uint16),
                 coh=coh.cpu().numpy(), ph=ph.cpu().numpy(), lam=lam.cpu().numpy(),
                 flags=flags.cpu().numpy(), kappa=kappa.cpu().numpy(), counters=cnt.cpu().numpy())
-
-
-def phase_errors(ph_gpu, ph_orc):
-    return np.abs(np.angle(ph_gpu * np.conj(ph_orc)))  # wrapped difference, [N, P]
-
-
-def well_posed(c: Case, coh_gpu):
-    dC = np.abs(coh_gpu.astype(np.complex128) - c.orc["coh"]).reshape(len(c.sens), -1)
-    eps = np.maximum(np.nanmax(np.where(np.isfinite(dC), dC, np.inf), axis=1), EPS_FLOOR)
-    return SAFETY * c.sens * eps <= PHASE_TOL
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -124,9 +109,11 @@ def test_coherence(gpu_lib, name, prec):
     g = gpu_path(gpu_lib, c, prec)
     # same masks (previous test), so the matrices are comparable pixel by pixel
     ok = np.all(np.isfinite(c.orc["coh"].reshape(len(c.sens), -1)), axis=1)
+    _, dmax = coherence_error(g["coh"], c.orc["coh"])
     d = np.abs(g["coh"][ok].astype(np.complex128) - c.orc["coh"][ok])
-    print(f"[parity] {name} {prec}: max |dC| {d.max():.3e}, mean {d.mean():.3e}")
-    assert d.max() <= COH_TOL
+    print(f"[parity] {name} {prec}: max |dC| {dmax:.3e}, mean {d.mean():.3e} (bound {EPS[prec]:.1e})")
+    assert dmax <= COH_TOL
+    assert dmax <= EPS[prec]  # the bound the phase criterion assumes
     # Hermitian with an exact unit diagonal
     gc = g["coh"][ok]
     assert np.all(gc[:, np.arange(c.wl.N), np.arange(c.wl.N)] == 1)
@@ -138,27 +125,19 @@ def test_coherence(gpu_lib, name, prec):
 def test_phase_link_on_oracle_coherence(gpu_lib, name):
     """The eigen-solver alone, fed the oracle's matrices rounded to complex64."""
     c = case(name)
-    P = len(c.sens)
     C64 = torch.from_numpy(c.orc["coh"].astype(np.complex64)).cuda()
     cnt = gpu_lib.new_counters()
     ph, lam, flags = gpu_lib.phase_link(C64, ref=c.ref, counters=cnt)
     ph, lam, flags = ph.cpu().numpy(), lam.cpu().numpy(), flags.cpu().numpy()
     link = c.orc["link"]
-    boundary = (link["min_pivot"] > O.TAU_PIVOT / 2) & (link["min_pivot"] < 2 * O.TAU_PIVOT)
-    same = (flags == link["flag"]) | boundary
-    assert same.all(), f"{int((~same).sum())} EMI/EVD decisions differ outside the boundary band"
-    dC = np.abs(c.orc["coh"].astype(np.complex64).astype(np.complex128) - c.orc["coh"]).reshape(P, -1)
-    eps = np.maximum(np.nanmax(np.where(np.isfinite(dC), dC, 0), axis=1), EPS_FLOOR)
-    wp = (SAFETY * c.sens * eps <= PHASE_TOL) & (flags == link["flag"])
+    dC, _ = coherence_error(c.orc["coh"].astype(np.complex64), c.orc["coh"])
     err = phase_errors(ph, link["phasor"])
-    worst = err[:, wp].max() if wp.any() else 0.0
-    print(f"[parity] {name}: well-posed {wp.mean():.4f}, max err {worst:.2e} rad, "
-          f"p99 all {np.percentile(err, 99):.2e}, counters {cnt.cpu().numpy()[:7]}")
-    assert wp.mean() > 0.9
-    assert worst <= PHASE_TOL
+    out = check_phases(f"{name} linking only", err, c.sens, flags, link, "fp32", dC_pix=dC,
+                       min_well_posed=len(c.sens) // 2, band=2.0)
+    print(f"[parity] {name}: counters {cnt.cpu().numpy()[:7]}")
     assert np.all(ph[c.ref] == 1)
-    # eigenvalue of the returned vector
-    emi = wp & (flags == 0)
+    # eigenvalue of the returned vector on well-posed EMI pixels
+    emi = (flags == 0) & (link["flag"] == 0) & (3 * c.sens * EPS["fp32"] <= PHASE_TOL)
     np.testing.assert_allclose(lam[emi], link["lam"][emi], rtol=1e-3)
 
 
@@ -168,13 +147,42 @@ def test_end_to_end_phases(gpu_lib, name, prec):
     c = case(name)
     g = gpu_path(gpu_lib, c, prec)
     link = c.orc["link"]
-    wp = well_posed(c, g["coh"]) & (g["flags"] == link["flag"])
+    dC, _ = coherence_error(g["coh"], c.orc["coh"])
     err = phase_errors(g["ph"], link["phasor"])
-    worst = err[:, wp].max()
-    print(f"[parity] {name} {prec}: well-posed {wp.mean():.4f}, max err {worst:.2e} rad, "
-          f"median all {np.median(err):.2e}")
-    assert wp.mean() > 0.85
-    assert worst <= PHASE_TOL
+    check_phases(f"{name} end to end", err, c.sens, g["flags"], link, prec, dC_pix=dC,
+                 min_well_posed=len(c.sens) // 2)
+    assert np.all(g["ph"][:, g["flags"] == O.FLAG_INVALID] == 1)
+
+
+# every linking-kernel variant (columns per row NJ = 12, 16, 20, 24, 28, 32; one
+# or two rows per lane) and both coherence tiles (16 and 32 images), with the
+# N = 15 + k stacks of the sequential scheme above 15 images
+VARIANT_N = [3, 8, 12, 13, 16, 17, 20, 21, 22, 24, 25, 28, 29, 32]
+
+
+@pytest.mark.parametrize("N", VARIANT_N)
+def test_linking_variants_against_oracle(gpu_lib, N):
+    n_new = min(N, 15)
+    wl = synth.Workload(f"variant{N}", 99, 198, n_new, N - n_new, (11, 5, 6, 3), model="burst")
+    z = synth.make_stack(wl, seed=300 + N)
+    ref = max(0, wl.n_comp - 1)
+    orc = O.link_ministack(z.numpy(), wl.n_comp, wl.window, wl.alpha, ref)
+    sens = sensitivity(orc["coh"], ref)
+    zc = z.cuda()
+    mean, var = gpu_lib.amplitude_stats(zc[wl.n_comp:].contiguous())
+    mask, _ = gpu_lib.shp_select(mean, var, wl.n_new, wl.window, wl.alpha)
+    _, _, _, stat = O.shp_select(orc["mean"], orc["var"], wl.n_new, wl.window, wl.alpha, return_stat=True)
+    band = np.abs(stat - O.glrt_threshold(wl.alpha)) < O.GLRT_BAND
+    diff = (O.mask_bits(mask.cpu().numpy().view(np.uint32), wl.window) != O.mask_bits(orc["mask"], wl.window))
+    assert not (diff & ~band).any()
+    for prec in ("fp32", "bf16"):
+        coh = gpu_lib.estimate_coherence(zc, mask, wl.window, precision=prec)
+        ph, lam, flags = gpu_lib.phase_link(coh, ref=ref)
+        dC, dmax = coherence_error(coh.cpu().numpy(), orc["coh"])
+        assert dmax <= min(COH_TOL, EPS[prec]), f"N={N} {prec}: max |dC| {dmax:.2e}"
+        err = phase_errors(ph.cpu().numpy(), orc["link"]["phasor"])
+        check_phases(f"N={N} (99x198)", err, sens, flags.cpu().numpy(), orc["link"], prec, dC_pix=dC,
+                     min_well_posed=len(sens) // 3)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -252,13 +260,11 @@ def test_upper_triangle_reading_above_16_images(gpu_lib):
     cond = np.linalg.cond(np.abs(Ch.astype(np.complex128)))
     orc = O.phase_link(Ch, ref=ref)
     ph, lam, flags = (t.cpu().numpy() for t in out[0])
-    sens = O.phase_sensitivity(Ch.astype(np.complex128), ref=ref)
-    wp = (SAFETY * sens * EPS_FLOOR <= PHASE_TOL) & (flags == orc["flag"])
-    err = np.abs(np.angle(ph * np.conj(orc["phasor"]))).max(axis=0)
-    print(f"[parity] upper triangle N={N}: max cond(|C|) {cond.max():.1e}, well-posed {wp.mean():.3f}, "
-          f"max err {err[wp].max():.2e} rad", flush=True)
-    assert wp.mean() > 0.8
-    assert err[wp].max() <= PHASE_TOL
+    sens = sensitivity(Ch.astype(np.complex128), ref)
+    print(f"[parity] upper triangle N={N}: max cond(|C|) {cond.max():.1e}", flush=True)
+    # the input is exactly Hermitian in FP32: only the solver's rounding remains
+    check_phases("upper triangle N=25", phase_errors(ph, orc["phasor"]), sens, flags, orc, "fp32",
+                 min_well_posed=P // 2, band=2.0)
 
 
 def test_nodata_pixels_are_invalid_and_ragged_grid(gpu_lib):
