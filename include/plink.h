@@ -90,8 +90,18 @@ enum {
     PL_CNT_NOT_CONVERGED = 4, /* eigenvector iterations that hit the cap */
     PL_CNT_SHIFT_RETRY = 5,   /* shifts rejected by the inertia check */
     PL_CNT_ITERS = 6,         /* total eigenvector iterations */
-    PL_NUM_COUNTERS = 8
+    PL_CNT_ITER_HIST = 8,     /* 16 entries: pixels by iteration count (entry
+                                 15: 15 or more), invalid pixels excluded */
+    PL_NUM_COUNTERS = 24
 };
+
+/* Host copy of a counters array (Sec. 3.2 expects the inverse power method to
+ * need "typically under 10 iterations"; the histogram shows how many did). */
+typedef struct {
+    int64_t glrt_band, glrt_recheck, evd_fallbacks, invalid, not_converged, shift_retries,
+        iterations;
+    int64_t iter_hist[16];
+} pl_report;
 
 /* ---------------------------------------------------------------- library */
 const char* pl_version(void);
@@ -102,6 +112,10 @@ const char* pl_last_error(void);
 pl_status pl_output_grid(int64_t R, int64_t C, pl_window w, int64_t* oR, int64_t* oC);
 /* Number of uint32 words per SHP mask, or 0 for an invalid window. */
 int32_t pl_mask_words(pl_window w);
+/* Waits for `stream`, then copies a device counters array (PL_NUM_COUNTERS
+ * uint64) into *out (host).  Errors of earlier kernels on the stream surface
+ * here as PL_ERR_HIP. */
+pl_status pl_sync_report(pl_stream stream, const uint64_t* counters, pl_report* out);
 
 /* -------------------------------------------------- amplitude statistics
  * Per-pixel mean and population variance of |z| over the M images of `slc`
@@ -154,12 +168,39 @@ pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64
  * phasors.  coh: [npix][N][N]; phasors: [N][npix] (phasors[ref_idx] = 1);
  * phase: [N][npix] or NULL, the same result as angles in (-pi, pi] (0 at
  * ref_idx and at invalid pixels); lambda: [npix] or NULL (eigenvalue of the vector: lambda_min of
- * |C|^{-1} o C for EMI, lambda_max of C for EVD); flags: [npix] or NULL
- * (PL_FLAG_*); invalid pixels (non-finite C) get phasors 1.
+ * |C|^{-1} o C for EMI, lambda_max of C for EVD); temp_coh: [npix] or NULL,
+ * the temporal coherence of the result (Sec. 3.3, eq. temporal-coherence):
+ * |sum_{i<k} exp(j(arg C_ik - (phi_i - phi_k)))| / (N(N-1)/2), with arg 0 = 0,
+ * 1 for N = 1 and 0 at invalid pixels; flags: [npix] or NULL (PL_FLAG_*);
+ * invalid pixels (non-finite C) get phasors 1.  For N > 16 C is read as the
+ * Hermitian matrix of its upper triangle.
  * counters: optional.  npix = 0 is a no-op (pointers may then be NULL). */
 pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
                         pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
-                        uint8_t* flags, uint64_t* counters, pl_stream stream);
+                        float* temp_coh, uint8_t* flags, uint64_t* counters, pl_stream stream);
+
+/* ------------------------------------- fused coherence + phase linking
+ * The sample coherence (eq. sample-coherence) of every output pixel linked
+ * straight away (Sec. 3.2) without a full-size coherence array: the output
+ * rows are processed in bands whose matrices, as packed upper triangles
+ * (N(N+1)/2 entries per pixel), live only in `workspace`.  Inputs as for
+ * pl_estimate_coherence; outputs as for pl_phase_link with npix = oR*oC
+ * (phasors / phase [N][oR*oC], lambda / temp_coh / flags [oR*oC], each
+ * optional except phasors).  The result equals pl_estimate_coherence followed
+ * by pl_phase_link, except that every N reads C as the Hermitian matrix of its
+ * upper triangle (for N <= 16 the two-step path reads full rows: the results
+ * then differ by the rounding of C's lower triangle).
+ * pl_phase_link_fused_workspace gives the bytes of one output row (the
+ * minimum) and of all rows; a workspace of B bytes processes
+ * B / min_bytes rows per band.  Errors: PL_ERR_WORKSPACE when ws_bytes <
+ * min_bytes. */
+pl_status pl_phase_link_fused_workspace(int32_t N, int64_t R, int64_t C, pl_window w, size_t* min_bytes,
+                                        size_t* all_rows_bytes);
+pl_status pl_phase_link_fused(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                              const uint32_t* mask, pl_precision prec, int32_t ref_idx,
+                              pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
+                              float* temp_coh, uint8_t* flags, uint64_t* counters, void* workspace,
+                              size_t ws_bytes, pl_stream stream);
 
 /* ------------------------------------------- adjoint of coherence + link
  * Vector-Jacobian product of the linked phases phi_i = arg(v_i conj(v_ref))
@@ -197,14 +238,68 @@ pl_status pl_compress_ministack(const pl_c64* stack, int32_t N, int32_t first_re
                                 int64_t C, pl_window w, const pl_c64* phasors, pl_c64* kappa,
                                 pl_stream stream);
 
+/* -------------------------------------- products of the linked phases */
+
+/* Persistent scatterers and regridding to the output grid (Sec. 3.1: the
+ * amplitude dispersion D_A = sigma_A / mu_A; Sec. 4: a threshold of 0.2;
+ * supplement "Regridding PS and DS to 30 m resolution").  A pixel is a PS
+ * iff mean > 0 and D_A <= da_threshold (D_A formed in FP64 from mean, var
+ * [R][C] float64, e.g. pl_amplitude_stats or the merged statistics).  Each
+ * output pixel takes the phasors ds_phasors [N][oR*oC] (its DS solution)
+ * when its block (the full-resolution pixels mapped to it as in
+ * pl_compress_ministack) holds no PS, else the single-reference phase
+ * z_i conj(z_ref_idx) of the block's PS with the lowest D_A (the first in
+ * row-major order on a tie) as unit phasors.  stack: [N][R][C];
+ * out_phasors: [N][oR*oC], may equal ds_phasors; ps_source: [oR*oC] int64
+ * flat index of the chosen PS or -1, or NULL; ps_mask: [R][C] uint8 (1 =
+ * PS), or NULL. */
+pl_status pl_ps_regrid(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w, int32_t ref_idx,
+                       const double* mean, const double* var, double da_threshold, const pl_c64* ds_phasors,
+                       pl_c64* out_phasors, int64_t* ps_source, uint8_t* ps_mask, pl_stream stream);
+
+/* Phase cosine similarity gamma_s (Sec. 3.3, eq. phase-cosine-sim) of linked
+ * phasors [N][oR*oC] on the output grid: for every neighbour q of p inside
+ * the disk of `radius` output pixels (1..15; p itself, pixels outside the grid
+ * and pixels whose flag is PL_FLAG_INVALID excluded),
+ * s = mean over the nearest-k network (pairs (a, b), 1 <= b - a <= k,
+ * k = 1..3; Sec. 3.4) of cos((phi_a - phi_b)(p) - (phi_a - phi_b)(q)), and
+ * gamma_s(p) is the median of these s (mean of the two middle values for an
+ * even count); 0 for an invalid p or one without neighbours.  flags: [oR*oC]
+ * or NULL; gamma_s: [oR*oC] float. */
+pl_status pl_phase_similarity(const pl_c64* phasors, int32_t N, int64_t oR, int64_t oC, const uint8_t* flags,
+                              int32_t radius, int32_t k, float* gamma_s, pl_stream stream);
+
+/* Interferograms of the nearest-k network of N dates (Sec. 3.4: 3N - 6 for
+ * k = 3), in the order the inversion reads them: by separation d = 1..k,
+ * then by first date a (pairs (a, a + d)).  Host helper. */
+pl_status pl_network_size(int32_t N, int32_t k, int32_t* n_ifg);
+
+/* L1 network inversion (Sec. 3.5, eq. l1-min): for every pixel, x in
+ * R^(N-1) (phases of dates 1..N-1 relative to date 0) minimising
+ * ||A x - b||_1, A the incidence matrix of the network (row of pair (a, b):
+ * +1 at date b, -1 at date a), by `iters` iterations of the ADMM of
+ * Appendix A from z = u = 0 with parameter rho, the Cholesky factor of A^T A
+ * shared by all pixels.  ifg: [n_ifg][P] float unwrapped interferogram
+ * phases (order of pl_network_size); x: [N-1][P] float; residual_l1: [P]
+ * float ||A x - b||_1 or NULL.  N = 2..32, k = 1..3; P = 0 is a no-op. */
+pl_status pl_network_invert_l1(const float* ifg, int32_t N, int32_t k, int64_t P, double rho, int32_t iters,
+                               float* x, float* residual_l1, pl_stream stream);
+
 /* ----------------------------------------------- sequential estimator
  * The mini-stack reference scheme of Sec. 2.2 (Fig. 1, "proposed
  * approach"): mini-stack k is [kappa_{k-K} .. kappa_{k-1} | M new SLCs]
  * with K = min(k, K_max); it is referenced to the most recent compressed SLC
  * (to its first image for k = 0), so every output is referenced to the first
  * date; earlier mini-stacks are never re-estimated.  The amplitude
- * statistics of mini-stacks k-K..k are merged with weights M
- * (eq. merged-mean/-variance) and n_eff = (K+1) M feeds the GLRT. */
+ * statistics of mini-stacks k-K..k are merged (eq. merged-mean/-variance)
+ * with weights M decay^age (age 0 = the current mini-stack; Sec. 3.1: even
+ * weights for decay = 1, an exponential decay that prioritises recent
+ * observations below 1) and n_eff = the sum of the weights feeds the GLRT.
+ * With reference = PL_SEQ_REF_LAST each compressed SLC is formed with the
+ * phasors re-referenced to the last real SLC of its mini-stack, so mini-stack
+ * k >= 1 is referenced to the last date of mini-stack k-1 (supplement,
+ * "Compressed SLC strategy for separate batched processing"). */
+enum { PL_SEQ_REF_COMPRESSED = 0, PL_SEQ_REF_LAST = 1 };
 typedef struct pl_seq pl_seq;
 
 typedef struct {
@@ -215,6 +310,8 @@ typedef struct {
     double alpha;       /* GLRT false-alarm rate */
     int32_t precision;  /* pl_precision */
     int32_t method;     /* pl_link_method */
+    int32_t reference;  /* PL_SEQ_REF_* */
+    double weight_decay; /* in (0, 1]; 1 = even weights */
 } pl_seq_params;
 
 /* Creates a driver; allocates its device state on the current device. */
@@ -228,6 +325,9 @@ pl_status pl_seq_count(const pl_seq* s, int64_t* count);
  * [oR*oC] or NULL; counters optional. */
 pl_status pl_seq_push(pl_seq* s, const pl_c64* new_slcs, pl_c64* phasors_out, pl_c64* kappa_out,
                       uint8_t* flags_out, uint64_t* counters, pl_stream stream);
+/* SHP masks ([oR][oC][nwords] uint32) of the most recent mini-stack, for
+ * inspection (enqueued on `stream`).  PL_ERR_STATE before the first push. */
+pl_status pl_seq_last_mask(const pl_seq* s, uint32_t* mask, pl_stream stream);
 /* Size in bytes of a checkpoint (compressed SLCs, statistics, counters). */
 pl_status pl_seq_state_size(const pl_seq* s, size_t* bytes);
 /* Writes the checkpoint into host memory (synchronises `stream`). */

@@ -20,14 +20,19 @@ __all__ = [
     "PlinkError", "load", "library_path", "output_grid", "mask_words", "amplitude_stats",
     "merge_amplitude_stats", "shp_select", "estimate_coherence", "phase_link",
     "compress_ministack", "Sequential", "new_counters", "phase_link_vjp", "phase_link_vjp_workspace",
+    "phase_link_fused", "phase_link_fused_workspace", "sync_report", "ps_regrid", "phase_similarity",
+    "network_size", "network_invert_l1",
     "PhaseLink", "Batch", "COUNTERS", "FLAG_EMI", "FLAG_EVD",
     "FLAG_INVALID", "MAX_N",
 ]
 
 MAX_N = 32
 FLAG_EMI, FLAG_EVD, FLAG_INVALID = 0, 1, 2
-#: names of the counters array entries (index = position)
+#: names of the counters array entries (index = position); entries 8..23 are
+#: the histogram of eigenvector iterations per pixel (see sync_report)
 COUNTERS = ("glrt_band", "glrt_recheck", "evd", "invalid", "not_converged", "shift_retry", "iters")
+NUM_COUNTERS = 24
+ITER_HIST = 8
 _PREC = {"fp32": 0, "bf16": 1, "split_bf16": 1}
 _METHOD = {"emi": 0, "evd": 1}
 
@@ -50,7 +55,20 @@ class _Window(ctypes.Structure):
 class _SeqParams(ctypes.Structure):
     _fields_ = [("R", ctypes.c_int64), ("C", ctypes.c_int64), ("M", ctypes.c_int32),
                 ("K_max", ctypes.c_int32), ("w", _Window), ("alpha", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("reference", ctypes.c_int32), ("weight_decay", ctypes.c_double)]
+
+    def __init__(self, R=0, C=0, M=0, K_max=0, w=None, alpha=1e-3, precision=0, method=0, reference=0,
+                 weight_decay=1.0):
+        super().__init__(R, C, M, K_max, w if w is not None else _Window(0, 0, 1, 1), alpha, precision, method,
+                         reference, weight_decay)
+
+
+class _Report(ctypes.Structure):
+    _fields_ = [("glrt_band", ctypes.c_int64), ("glrt_recheck", ctypes.c_int64),
+                ("evd_fallbacks", ctypes.c_int64), ("invalid", ctypes.c_int64),
+                ("not_converged", ctypes.c_int64), ("shift_retries", ctypes.c_int64),
+                ("iterations", ctypes.c_int64), ("iter_hist", ctypes.c_int64 * 16)]
 
 
 class _BatchItem(ctypes.Structure):
@@ -75,7 +93,16 @@ _SIGNATURES = {
     "pl_merge_amplitude_stats": (ctypes.c_int, [_P, _P, ctypes.POINTER(_D), _I32, _I64, _I64, _P, _P, _P]),
     "pl_shp_select": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _Window, _D, _P, _P, _P, _P]),
     "pl_estimate_coherence": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, ctypes.c_int, _P, _P]),
-    "pl_phase_link": (ctypes.c_int, [_P, _I32, _I64, _I32, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "pl_phase_link": (ctypes.c_int, [_P, _I32, _I64, _I32, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P]),
+    "pl_sync_report": (ctypes.c_int, [_P, _P, ctypes.POINTER(_Report)]),
+    "pl_phase_link_fused_workspace": (ctypes.c_int, [_I32, _I64, _I64, _Window, ctypes.POINTER(ctypes.c_size_t),
+                                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "pl_phase_link_fused": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, ctypes.c_int, _I32, ctypes.c_int,
+                                           _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pl_ps_regrid": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _I32, _P, _P, _D, _P, _P, _P, _P, _P]),
+    "pl_phase_similarity": (ctypes.c_int, [_P, _I32, _I64, _I64, _P, _I32, _I32, _P, _P]),
+    "pl_network_size": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(_I32)]),
+    "pl_network_invert_l1": (ctypes.c_int, [_P, _I32, _I32, _I64, _D, _I32, _P, _P, _P]),
     "pl_phase_link_vjp_workspace": (ctypes.c_int, [_I32, _I64, _I64, _Window, ctypes.POINTER(ctypes.c_size_t)]),
     "pl_phase_link_vjp": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, _P, _I32, ctypes.c_int, _P, _P,
                                          _P, ctypes.c_size_t, _P]),
@@ -90,6 +117,7 @@ _SIGNATURES = {
     "pl_seq_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
     "pl_seq_push": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "pl_seq_state_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "pl_seq_last_mask": (ctypes.c_int, [_P, _P, _P]),
     "pl_seq_save": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "pl_seq_load": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
 }
@@ -160,7 +188,19 @@ def mask_words(window) -> int:
 
 def new_counters(device="cuda"):
     """Zeroed device counter array (see COUNTERS for the entries)."""
-    return torch.zeros(8, dtype=torch.int64, device=device)
+    return torch.zeros(NUM_COUNTERS, dtype=torch.int64, device=device)
+
+
+def sync_report(counters: torch.Tensor) -> dict:
+    """Waits for the current stream and returns the counters as a dict, with
+    the iteration histogram under "iter_hist" (entry 15: 15 or more)."""
+    if counters.dtype != torch.int64 or counters.numel() < NUM_COUNTERS or not counters.is_contiguous():
+        raise PlinkError("sync_report: expected a contiguous int64 counters tensor")
+    rep = _Report()
+    _check(load().pl_sync_report(_stream(counters), _ptr(counters), ctypes.byref(rep)), "sync_report")
+    out = {k: getattr(rep, k) for k, _ in _Report._fields_ if k != "iter_hist"}
+    out["iter_hist"] = list(rep.iter_hist)
+    return out
 
 
 def amplitude_stats(slc: torch.Tensor):
@@ -218,20 +258,125 @@ def estimate_coherence(stack: torch.Tensor, mask: torch.Tensor, window, precisio
     return coh
 
 
-def phase_link(coh: torch.Tensor, ref: int = 0, method="emi", counters=None, want_phase=False):
+def phase_link(coh: torch.Tensor, ref: int = 0, method="emi", counters=None, want_phase=False,
+               want_tcoh=False):
     """EMI (EVD fallback) linked phasors: [P,N,N] -> (phasors [N,P], lambda [P], flags uint8 [P]),
-    plus the phases [N,P] (float32, radians) as a fourth element when want_phase."""
+    followed by the phases [N,P] (float32, radians) when want_phase and the
+    temporal coherence [P] (float32) when want_tcoh."""
     _need(coh, torch.complex64, 3, "phase_link")
     P, N, N2 = coh.shape
     if N != N2:
         raise PlinkError("phase_link: matrices must be square")
     ph = torch.empty((N, P), dtype=torch.complex64, device=coh.device)
     phase = torch.empty((N, P), dtype=torch.float32, device=coh.device) if want_phase else None
+    tcoh = torch.empty((P,), dtype=torch.float32, device=coh.device) if want_tcoh else None
     lam = torch.empty((P,), dtype=torch.float32, device=coh.device)
     flags = torch.empty((P,), dtype=torch.uint8, device=coh.device)
     _check(load().pl_phase_link(_ptr(coh), N, P, int(ref), _METHOD[method], _ptr(ph), _ptr(phase),
-                                _ptr(lam), _ptr(flags), _ptr(counters), _stream(coh)), "phase_link")
-    return (ph, lam, flags, phase) if want_phase else (ph, lam, flags)
+                                _ptr(lam), _ptr(tcoh), _ptr(flags), _ptr(counters), _stream(coh)), "phase_link")
+    out = (ph, lam, flags)
+    if want_phase:
+        out += (phase,)
+    if want_tcoh:
+        out += (tcoh,)
+    return out
+
+
+def phase_link_fused_workspace(N: int, R: int, C: int, window):
+    """(bytes of one output row, bytes of all rows) of packed coherence."""
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().pl_phase_link_fused_workspace(int(N), int(R), int(C), _win(window), ctypes.byref(a),
+                                                ctypes.byref(b)), "phase_link_fused_workspace")
+    return a.value, b.value
+
+
+def phase_link_fused(stack: torch.Tensor, mask: torch.Tensor, window, ref: int = 0, precision="fp32",
+                     method="emi", counters=None, workspace: torch.Tensor | None = None,
+                     want_phase=False, want_tcoh=False):
+    """Coherence straight into phase linking, band by band through
+    `workspace` (uint8 device tensor; default: every output row at once).
+    Returns (phasors [N, oR*oC], lambda, flags[, phase][, tcoh]) like
+    phase_link."""
+    _need(stack, torch.complex64, 3, "phase_link_fused")
+    _need(mask, torch.int32, 3, "phase_link_fused mask")
+    N, R, C = stack.shape
+    oR, oC = output_grid(R, C, window)
+    if tuple(mask.shape) != (oR, oC, mask_words(window)):
+        raise PlinkError("phase_link_fused: mask shape does not match the window")
+    if workspace is None:
+        workspace = torch.empty((phase_link_fused_workspace(N, R, C, window)[1],), dtype=torch.uint8,
+                                device=stack.device)
+    P = oR * oC
+    dev = stack.device
+    ph = torch.empty((N, P), dtype=torch.complex64, device=dev)
+    phase = torch.empty((N, P), dtype=torch.float32, device=dev) if want_phase else None
+    tcoh = torch.empty((P,), dtype=torch.float32, device=dev) if want_tcoh else None
+    lam = torch.empty((P,), dtype=torch.float32, device=dev)
+    flags = torch.empty((P,), dtype=torch.uint8, device=dev)
+    _check(load().pl_phase_link_fused(_ptr(stack), N, R, C, _win(window), _ptr(mask), _PREC[precision], int(ref),
+                                      _METHOD[method], _ptr(ph), _ptr(phase), _ptr(lam), _ptr(tcoh), _ptr(flags),
+                                      _ptr(counters), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _stream(stack)),
+           "phase_link_fused")
+    out = (ph, lam, flags)
+    if want_phase:
+        out += (phase,)
+    if want_tcoh:
+        out += (tcoh,)
+    return out
+
+
+def ps_regrid(stack: torch.Tensor, ref: int, window, mean: torch.Tensor, var: torch.Tensor,
+              ds_phasors: torch.Tensor, threshold: float = 0.2, inplace=False):
+    """PS selection (D_A <= threshold) and PS/DS regridding: -> (phasors
+    [N, oR*oC], PS source index int64 [oR*oC] (-1: DS), PS mask uint8 [R,C])."""
+    _need(stack, torch.complex64, 3, "ps_regrid")
+    _need(mean, torch.float64, 2, "ps_regrid mean")
+    _need(var, torch.float64, 2, "ps_regrid var")
+    N, R, C = stack.shape
+    oR, oC = output_grid(R, C, window)
+    if ds_phasors.dtype != torch.complex64 or ds_phasors.numel() != N * oR * oC or not ds_phasors.is_contiguous():
+        raise PlinkError("ps_regrid: ds_phasors must be contiguous complex64 [N, oR*oC]")
+    out = ds_phasors if inplace else torch.empty((N, oR * oC), dtype=torch.complex64, device=stack.device)
+    src = torch.empty((oR * oC,), dtype=torch.int64, device=stack.device)
+    ps = torch.empty((R, C), dtype=torch.uint8, device=stack.device)
+    _check(load().pl_ps_regrid(_ptr(stack), N, R, C, _win(window), int(ref), _ptr(mean), _ptr(var), float(threshold),
+                               _ptr(ds_phasors), _ptr(out), _ptr(src), _ptr(ps), _stream(stack)), "ps_regrid")
+    return out, src, ps
+
+
+def phase_similarity(phasors: torch.Tensor, out_shape, radius: int, k: int = 3, flags=None):
+    """gamma_s [oR*oC] (float32) of linked phasors [N, oR*oC]."""
+    oR, oC = out_shape
+    if phasors.dtype != torch.complex64 or phasors.dim() != 2 or phasors.shape[1] != oR * oC \
+            or not phasors.is_contiguous():
+        raise PlinkError("phase_similarity: phasors must be contiguous complex64 [N, oR*oC]")
+    if flags is not None and (flags.dtype != torch.uint8 or flags.numel() != oR * oC or not flags.is_contiguous()):
+        raise PlinkError("phase_similarity: flags must be contiguous uint8 [oR*oC]")
+    out = torch.empty((oR * oC,), dtype=torch.float32, device=phasors.device)
+    _check(load().pl_phase_similarity(_ptr(phasors), phasors.shape[0], oR, oC, _ptr(flags), int(radius), int(k),
+                                      _ptr(out), _stream(phasors)), "phase_similarity")
+    return out
+
+
+def network_size(N: int, k: int = 3) -> int:
+    n = _I32()
+    _check(load().pl_network_size(int(N), int(k), ctypes.byref(n)), "network_size")
+    return n.value
+
+
+def network_invert_l1(ifg: torch.Tensor, N: int, k: int = 3, rho: float = 1.0, iters: int = 200):
+    """L1 inversion of unwrapped interferograms [n_ifg, P] (float32) of the
+    nearest-k network: -> (x [N-1, P], residual ||Ax - b||_1 [P])."""
+    _need(ifg, torch.float32, 2, "network_invert_l1")
+    if ifg.shape[0] != network_size(N, k):
+        raise PlinkError("network_invert_l1: ifg rows do not match the network")
+    P = ifg.shape[1]
+    x = torch.empty((N - 1, P), dtype=torch.float32, device=ifg.device)
+    res = torch.empty((P,), dtype=torch.float32, device=ifg.device)
+    _check(load().pl_network_invert_l1(_ptr(ifg), int(N), int(k), P, float(rho), int(iters), _ptr(x), _ptr(res),
+                                       _stream(ifg)), "network_invert_l1")
+    return x, res
 
 
 def phase_link_vjp_workspace(N: int, R: int, C: int, window) -> int:
@@ -270,18 +415,17 @@ def phase_link_vjp(stack: torch.Tensor, mask: torch.Tensor, flags: torch.Tensor,
 
 class PhaseLink(torch.autograd.Function):
     """Linked phases [N, oR, oC] of a stack [N, R, C] (complex64) for a fixed SHP
-    mask, differentiable with respect to the stack.  The forward runs the
-    coherence and linking kernels; the backward recomputes the coherence and
-    the eigen-solve inside the adjoint kernels (only the stack, the mask and
-    the per-pixel EMI/EVD flags are kept)."""
+    mask, differentiable with respect to the stack.  The forward is the fused
+    coherence + linking entry point (no full-size coherence array); the
+    backward recomputes the coherence and the eigen-solve inside the adjoint
+    kernels (only the stack, the mask and the per-pixel EMI/EVD flags are
+    kept)."""
 
     @staticmethod
     def forward(ctx, stack, mask, window, ref=0, precision="fp32", method="emi"):
         N, R, C = stack.shape
         oR, oC = output_grid(R, C, window)
-        coh = estimate_coherence(stack, mask, window, precision)
-        _, _, flags, phase = phase_link(coh, ref, method, want_phase=True)
-        del coh
+        _, _, flags, phase = phase_link_fused(stack, mask, window, ref, precision, method, want_phase=True)
         ctx.save_for_backward(stack, mask, flags)
         ctx.window, ctx.ref, ctx.precision = tuple(window), int(ref), precision
         ctx.mark_non_differentiable(flags)
@@ -412,19 +556,28 @@ class SequentialParams:
     alpha: float = 1e-3
     precision: str = "fp32"
     method: str = "emi"
+    reference: str = "compressed"
+    weight_decay: float = 1.0
+
+
+_REFERENCE = {"compressed": 0, "last": 1}
 
 
 class Sequential:
-    """Sequential estimator (mini-stack reference scheme, compressed SLCs)."""
+    """Sequential estimator (mini-stack reference scheme, compressed SLCs).
+    reference="last" forms the compressed SLCs referenced to the last real
+    SLC of each mini-stack; weight_decay < 1 weights older statistics
+    exponentially less."""
 
     def __init__(self, R, C, M, K_max, window, alpha=1e-3, precision="fp32", method="emi",
-                 device="cuda"):
+                 device="cuda", reference="compressed", weight_decay=1.0):
         lib = load()
-        self.params = SequentialParams(R, C, M, K_max, tuple(window), alpha, precision, method)
+        self.params = SequentialParams(R, C, M, K_max, tuple(window), alpha, precision, method, reference,
+                                       weight_decay)
         self.device = torch.device(device)
         self.out_shape = output_grid(R, C, window)
         p = _SeqParams(int(R), int(C), int(M), int(K_max), _win(window), float(alpha),
-                       _PREC[precision], _METHOD[method])
+                       _PREC[precision], _METHOD[method], _REFERENCE[reference], float(weight_decay))
         h = _P()
         with torch.cuda.device(self.device):
             _check(lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)), "Sequential")
@@ -461,6 +614,14 @@ class Sequential:
         _check(load().pl_seq_push(self._h, _ptr(new_slcs), _ptr(ph), _ptr(kap), _ptr(fl),
                                   _ptr(counters), _stream(new_slcs)), "Sequential.push")
         return ph, kap, fl
+
+    def last_mask(self) -> torch.Tensor:
+        """SHP masks [oR, oC, nwords] (int32 holding uint32 bits) of the most
+        recent mini-stack."""
+        oR, oC = self.out_shape
+        m = torch.empty((oR, oC, mask_words(self.params.window)), dtype=torch.int32, device=self.device)
+        _check(load().pl_seq_last_mask(self._h, _ptr(m), _stream(m)), "Sequential.last_mask")
+        return m
 
     def save(self) -> bytes:
         n = ctypes.c_size_t()

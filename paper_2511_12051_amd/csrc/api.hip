@@ -77,6 +77,60 @@ static hipStream_t S(pl_stream s) { return reinterpret_cast<hipStream_t>(s); }
         if (!(cond)) return fail(status, __VA_ARGS__); \
     } while (0)
 
+// ---- fused coherence + linking over bands of output rows
+static size_t fused_row_bytes(int N, const Geometry& g) {
+    return (size_t)g.oC * (size_t)(N * (N + 1) / 2) * sizeof(float2);
+}
+
+namespace plk {
+namespace {
+// the checked body shared by the fused entry points: rows per band from the
+// buffer size, then per band one coherence launch into the buffer and one
+// linking launch out of it (stream order separates the bands)
+pl_status fused_run(const pl_c64* stack, int32_t N, const Geometry& g, const uint32_t* mask, pl_precision prec,
+                    int32_t ref_idx, pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
+                    float* temp_coh, uint8_t* flags, uint64_t* counters, float2* buf, size_t buf_bytes,
+                    hipStream_t s) {
+    const size_t row = fused_row_bytes(N, g);
+    int64_t rows = (int64_t)(buf_bytes / row);
+    if (rows > g.oR) rows = g.oR;
+    const int64_t P = g.oR * g.oC;
+    PlaneTable t = contiguous_planes(stack, N, g.R * g.C);
+    for (int64_t a = 0; a < g.oR; a += rows) {
+        const int64_t b = a + rows < g.oR ? a + rows : g.oR;
+        pl_status r = launch_coherence_rows(t, N, g, mask, (int)prec, buf, 1, a, b, s);
+        if (r != PL_OK) return r;
+        const int64_t off = a * g.oC;
+        LinkArgs la = link_args(buf, N, (b - a) * g.oC, ref_idx, (int)method,
+                                reinterpret_cast<float2*>(phasors) + off, phase ? phase + off : nullptr,
+                                lambda ? lambda + off : nullptr, flags ? flags + off : nullptr,
+                                reinterpret_cast<unsigned long long*>(counters));
+        la.tcoh = temp_coh ? temp_coh + off : nullptr;
+        la.packed = 1;
+        la.ostride = P;
+        r = launch_phase_link(la, s);
+        if (r != PL_OK) return r;
+    }
+    return PL_OK;
+}
+
+pl_status fused_check(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w, const uint32_t* mask,
+                      pl_precision prec, int32_t ref_idx, pl_link_method method, const pl_c64* phasors,
+                      const char* who, Geometry* g) {
+    PL_CHECK(stack && mask && phasors, PL_ERR_INVALID_ARG, "%s: NULL pointer", who);
+    PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "%s: N=%d outside 1..%d", who, N, kMaxN);
+    PL_CHECK(make_geometry(R, C, w, g), PL_ERR_SHAPE, "%s: bad image size or window", who);
+    PL_CHECK(g->oR >= 1 && g->oC >= 1, PL_ERR_SHAPE, "%s: image smaller than one stride", who);
+    PL_CHECK(ref_idx >= 0 && ref_idx < N, PL_ERR_INVALID_ARG, "%s: ref_idx %d outside 0..%d", who, ref_idx, N - 1);
+    PL_CHECK(prec == PL_PREC_FP32 || prec == PL_PREC_SPLIT_BF16, PL_ERR_INVALID_ARG, "%s: unknown precision %d",
+             who, (int)prec);
+    PL_CHECK(method == PL_LINK_EMI || method == PL_LINK_EVD, PL_ERR_INVALID_ARG, "%s: unknown method %d", who,
+             (int)method);
+    return PL_OK;
+}
+}  // namespace
+}  // namespace plk
+
 extern "C" {
 
 const char* pl_version(void) { return "plink 0.1 (gfx950)"; }
@@ -166,9 +220,27 @@ pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64
     return launch_coherence(t, N, g, mask, (int)prec, reinterpret_cast<float2*>(coh), nullptr, S(stream));
 }
 
+pl_status pl_sync_report(pl_stream stream, const uint64_t* counters, pl_report* out) {
+    PL_CHECK(counters && out, PL_ERR_INVALID_ARG, "pl_sync_report: NULL pointer");
+    uint64_t h[PL_NUM_COUNTERS];
+    pl_status r = hip_ok(hipStreamSynchronize(S(stream)), "pl_sync_report: synchronize");
+    if (r != PL_OK) return r;
+    r = hip_ok(hipMemcpy(h, counters, sizeof h, hipMemcpyDeviceToHost), "pl_sync_report: copy");
+    if (r != PL_OK) return r;
+    out->glrt_band = (int64_t)h[PL_CNT_GLRT_BAND];
+    out->glrt_recheck = (int64_t)h[PL_CNT_GLRT_RECHECK];
+    out->evd_fallbacks = (int64_t)h[PL_CNT_EVD];
+    out->invalid = (int64_t)h[PL_CNT_INVALID];
+    out->not_converged = (int64_t)h[PL_CNT_NOT_CONVERGED];
+    out->shift_retries = (int64_t)h[PL_CNT_SHIFT_RETRY];
+    out->iterations = (int64_t)h[PL_CNT_ITERS];
+    for (int b = 0; b < 16; ++b) out->iter_hist[b] = (int64_t)h[PL_CNT_ITER_HIST + b];
+    return PL_OK;
+}
+
 pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
                         pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
-                        uint8_t* flags, uint64_t* counters, pl_stream stream) {
+                        float* temp_coh, uint8_t* flags, uint64_t* counters, pl_stream stream) {
     PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_phase_link: N=%d outside 1..%d", N, kMaxN);
     PL_CHECK(npix >= 0, PL_ERR_SHAPE, "pl_phase_link: negative pixel count");
     PL_CHECK(npix == 0 || (coh && phasors), PL_ERR_INVALID_ARG, "pl_phase_link: NULL pointer");
@@ -177,9 +249,39 @@ pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_
     PL_CHECK(method == PL_LINK_EMI || method == PL_LINK_EVD, PL_ERR_INVALID_ARG,
              "pl_phase_link: unknown method %d", (int)method);
     if (npix == 0) return PL_OK;
-    return launch_phase_link(reinterpret_cast<const float2*>(coh), N, npix, ref_idx, (int)method,
-                             reinterpret_cast<float2*>(phasors), phase, lambda, flags,
-                             reinterpret_cast<unsigned long long*>(counters), S(stream));
+    LinkArgs a = link_args(reinterpret_cast<const float2*>(coh), N, npix, ref_idx, (int)method,
+                           reinterpret_cast<float2*>(phasors), phase, lambda, flags,
+                           reinterpret_cast<unsigned long long*>(counters));
+    a.tcoh = temp_coh;
+    return launch_phase_link(a, S(stream));
+}
+
+pl_status pl_phase_link_fused_workspace(int32_t N, int64_t R, int64_t C, pl_window w, size_t* min_bytes,
+                                        size_t* all_rows_bytes) {
+    Geometry g;
+    PL_CHECK(min_bytes || all_rows_bytes, PL_ERR_INVALID_ARG, "pl_phase_link_fused_workspace: NULL output");
+    PL_CHECK(N >= 1 && N <= kMaxN, PL_ERR_UNSUPPORTED, "pl_phase_link_fused_workspace: N=%d outside 1..%d", N, kMaxN);
+    PL_CHECK(make_geometry(R, C, w, &g), PL_ERR_SHAPE, "pl_phase_link_fused_workspace: bad image size or window");
+    PL_CHECK(g.oR >= 1 && g.oC >= 1, PL_ERR_SHAPE, "pl_phase_link_fused_workspace: image smaller than one stride");
+    if (min_bytes) *min_bytes = fused_row_bytes(N, g);
+    if (all_rows_bytes) *all_rows_bytes = fused_row_bytes(N, g) * (size_t)g.oR;
+    return PL_OK;
+}
+
+
+pl_status pl_phase_link_fused(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                              const uint32_t* mask, pl_precision prec, int32_t ref_idx,
+                              pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
+                              float* temp_coh, uint8_t* flags, uint64_t* counters, void* workspace,
+                              size_t ws_bytes, pl_stream stream) {
+    Geometry g;
+    pl_status r = fused_check(stack, N, R, C, w, mask, prec, ref_idx, method, phasors, "pl_phase_link_fused", &g);
+    if (r != PL_OK) return r;
+    PL_CHECK(workspace, PL_ERR_INVALID_ARG, "pl_phase_link_fused: NULL workspace");
+    PL_CHECK(ws_bytes >= fused_row_bytes(N, g), PL_ERR_WORKSPACE,
+             "pl_phase_link_fused: workspace of %zu bytes, one output row needs %zu", ws_bytes, fused_row_bytes(N, g));
+    return fused_run(stack, N, g, mask, prec, ref_idx, method, phasors, phase, lambda, temp_coh, flags, counters,
+                     static_cast<float2*>(workspace), ws_bytes, S(stream));
 }
 
 // workspace of the adjoint: C [P][N][N] c64 | diag(A) [P][N] f32 |

@@ -406,14 +406,17 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             a.g = g;
             a.mask = mask;
             a.coh = coh;
+            a.packed = 0;
+            a.oy_lo = 0;
+            a.oy_hi = g.oR;
             a.n_pairs = g.wy * (g.hx + 1);
             Group<CohArgs>& cg = L.coh[it.N <= 16 ? 0 : 1];
             cg.variant = it.N <= 16 ? 16 : 32;
             add_member(cg, k, a, 0);  // blocks set by configure_coherence
         }
         {
-            LinkArgs a{coh, it.N, P, it.ref_idx, (int)method, reinterpret_cast<float2*>(it.phasors), nullptr,
-                       nullptr, it.flags, nullptr};
+            const LinkArgs a = link_args(coh, it.N, P, it.ref_idx, (int)method, reinterpret_cast<float2*>(it.phasors),
+                                         nullptr, nullptr, it.flags, nullptr);
             Group<LinkArgs>& lg = L.link[(it.N + 3) / 4];
             lg.variant = (it.N + 3) / 4;
             add_member(lg, k, a, link_blocks(it.N, P));

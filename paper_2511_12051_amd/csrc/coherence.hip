@@ -316,16 +316,18 @@ __device__ void store_pixel(const CohArgs& a, float* S, const typename Acc<NT>::
     // hardware reciprocal square roots (about 1 ulp), far inside the coherence tolerance
     const float isj = __builtin_amdgcn_rsqf(dj);
     if (a.diag && lane < NT && j < N) a.diag[pix * N + j] = dj;
-    float2* out = a.coh + pix * (int64_t)N * N;
+    const int packed = a.packed;
+    float2* out = a.coh + pix * (int64_t)(packed ? (N * (N + 1)) >> 1 : N * N);
 #pragma unroll
     for (int v = 0; v < Acc<NT>::R; ++v) {
         const int i = Acc<NT>::row(lane, v);
-        if (i < N && j < N) {
+        if (i < N && j < N && (!packed || i <= j)) {
             const float isi = __builtin_amdgcn_rsqf(diag[i]);
             float2 c = make_float2(re[v] * isi * isj, im[v] * isi * isj);
             if (i == j) c = make_float2(1.f, 0.f);
             if (invalid) c = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-            out[i * N + j] = c;
+            // packed: entry (i, j >= i) of the row-major upper triangle
+            out[packed ? ((i * (2 * N - i - 1)) >> 1) + j : i * N + j] = c;
         }
     }
     wave_sync();
@@ -434,8 +436,8 @@ __device__ void coherence_body(const CohArgs& a, const float2* const* planes, in
     const int lane = lane_id();
     const int64_t ox0 = strip * a.TXo;
     const int64_t ox1 = ox0 + a.TXo < g.oC ? ox0 + a.TXo : g.oC;
-    const int64_t oy0 = band * a.rows_per_wg;
-    const int64_t oy1 = oy0 + a.rows_per_wg < g.oR ? oy0 + a.rows_per_wg : g.oR;
+    const int64_t oy0 = a.oy_lo + band * a.rows_per_wg;
+    const int64_t oy1 = oy0 + a.rows_per_wg < a.oy_hi ? oy0 + a.rows_per_wg : a.oy_hi;
     const int64_t x0 = (ox0 * g.sx + g.sx / 2 - g.hx) & ~(int64_t)1;
     const int data_words = 4 * a.N * a.plane;  // one 16-byte record per pixel pair
     uint32_t* wave_area = lds_words + data_words + wave * a.wave_words;
@@ -470,7 +472,7 @@ __device__ void coherence_body(const CohArgs& a, const float2* const* planes, in
             wave_sync();
             typename Acc<NT>::T re, im;
             pixel_gram<NT, SPLIT>(a, lds_words, wave_area, npad, lane, re, im, S);
-            store_pixel<NT>(a, S, re, im, oy * g.oC + ox, lane);
+            store_pixel<NT>(a, S, re, im, (oy - a.oy_lo) * g.oC + ox, lane);
         }
         __syncthreads();  // every wave is done with the rows about to be replaced
         if (more) {
@@ -550,12 +552,13 @@ size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req
     a.n_strips = (g.oC + chosen - 1) / chosen;
     int64_t rows = rows_req;
     if (rows <= 0) {  // enough workgroups to fill the chip several times over
-        rows = (g.oR * a.n_strips + 2047) / 2048;
+        rows = ((a.oy_hi - a.oy_lo) * a.n_strips + 2047) / 2048;
         if (rows < 4) rows = 4;
     }
-    if (rows > g.oR) rows = g.oR;
+    const int64_t nrows = a.oy_hi - a.oy_lo;
+    if (rows > nrows) rows = nrows;
     a.rows_per_wg = (int)rows;
-    *blocks = a.n_strips * ((g.oR + rows - 1) / rows);
+    *blocks = a.n_strips * ((nrows + rows - 1) / rows);
     return lds;
 }
 
@@ -568,6 +571,31 @@ pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const 
     a.g = g;
     a.mask = mask;
     a.coh = coh;
+    a.packed = 0;
+    a.oy_lo = 0;
+    a.oy_hi = g.oR;
+    return launch_coherence_args(a, prec, s);
+}
+
+pl_status launch_coherence_rows(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
+                                int prec, float2* coh, int packed, int64_t oy_lo, int64_t oy_hi,
+                                hipStream_t s) {
+    CohArgs a{};
+    a.diag = nullptr;
+    a.t = t;
+    a.N = N;
+    a.g = g;
+    a.mask = mask;
+    a.coh = coh;
+    a.packed = packed;
+    a.oy_lo = oy_lo;
+    a.oy_hi = oy_hi;
+    return launch_coherence_args(a, prec, s);
+}
+
+pl_status launch_coherence_args(CohArgs& a, int prec, hipStream_t s) {
+    const Geometry& g = a.g;
+    const int N = a.N;
     a.n_pairs = g.wy * (g.hx + 1);
     const bool split = prec == PL_PREC_SPLIT_BF16;
     const int nt = N <= 16 ? 16 : 32;

@@ -33,6 +33,12 @@ __device__ __forceinline__ void compress_body(const CompressArgs& a, int64_t blo
         re = fmaf(w.x, z.x, fmaf(w.y, z.y, re));
         im = fmaf(w.x, z.y, fmaf(-w.y, z.x, im));
     }
+    if (a.rot >= 0) {  // times phasor rot: the sum re-referenced to image rot
+        const float2 w = ph[(int64_t)a.rot * opix + b];
+        const float r2 = re * w.x - im * w.y;
+        im = re * w.y + im * w.x;
+        re = r2;
+    }
     kappa[p] = make_float2(re, im);
 }
 
@@ -51,16 +57,17 @@ __global__ __launch_bounds__(kBlock) void compress_batch(BatchRange<CompressArgs
 
 CompressArgs compress_args(const PlaneTable& t, int N, int first_real, const Geometry& g,
                            const float2* phasors, float2* kappa, int64_t* blocks) {
-    CompressArgs a{t, N, first_real, g, phasors, kappa, (g.C + kBlock - 1) / kBlock};
+    CompressArgs a{t, N, first_real, g, phasors, kappa, (g.C + kBlock - 1) / kBlock, -1};
     *blocks = a.gx * g.R;
     return a;
 }
 
 pl_status launch_compress(const PlaneTable& t, int N, int first_real, const Geometry& g,
-                          const float2* phasors, float2* kappa, hipStream_t s) {
+                          const float2* phasors, float2* kappa, hipStream_t s, int rot) {
     if (g.R > 2147483647LL) return fail(PL_ERR_UNSUPPORTED, "pl_compress_ministack: too many rows");
     int64_t blocks;
-    const CompressArgs a = compress_args(t, N, first_real, g, phasors, kappa, &blocks);
+    CompressArgs a = compress_args(t, N, first_real, g, phasors, kappa, &blocks);
+    a.rot = rot;
     dim3 grid((unsigned)a.gx, (unsigned)g.R);
     hipLaunchKernelGGL(compress_kernel, grid, dim3(kBlock), 0, s, a);
     return launch_ok("compress kernel");

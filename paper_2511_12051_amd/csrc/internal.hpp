@@ -64,8 +64,11 @@ struct CohArgs {
     int N;
     Geometry g;
     const uint32_t* mask;
-    float2* coh;
+    float2* coh;      // [P][N][N], or [P][N(N+1)/2] upper triangles when packed
     float* diag;      // optional [P][N] diagonal of A (SHP-summed |z|^2), or null
+    int packed;       // write each matrix as its packed upper triangle
+    int64_t oy_lo, oy_hi;  // output rows of this launch; pixel p of coh is
+                           // (oy_lo + p / oC, p % oC)
     int TXo;          // output columns per strip
     int rows_per_wg;  // output rows per workgroup
     int tile_w;       // staged input columns (even)
@@ -79,16 +82,19 @@ struct CohArgs {
 };
 
 struct LinkArgs {
-    const float2* coh;
+    const float2* coh;  // [npix][N][N], or packed upper triangles [npix][N(N+1)/2]
     int N;
     int64_t npix;
     int ref;
     int method;
-    float2* ph;
-    float* phase;  // optional [N][npix] angles in (-pi, pi], 0 at the reference
-    float* lam;
-    uint8_t* flags;
+    float2* ph;         // [N][ostride] (pixel p of image i at ph[i * ostride + p])
+    float* phase;       // optional, same layout: angles in (-pi, pi], 0 at the reference
+    float* lam;         // optional [npix]
+    uint8_t* flags;     // optional [npix]
     unsigned long long* counters;
+    float* tcoh;        // optional [npix] temporal coherence of the linked phases
+    int packed;         // coh layout
+    int64_t ostride;    // image stride of ph / phase (>= npix)
 };
 
 struct CompressArgs {
@@ -98,6 +104,7 @@ struct CompressArgs {
     const float2* ph;
     float2* kappa;
     int64_t gx;  // blocks per image row
+    int rot;     // >= 0: kappa multiplied by phasor rot of its block (re-reference)
 };
 
 template <typename Args>
@@ -115,9 +122,15 @@ pl_status launch_shp_select(const double* mean, const double* var, const Geometr
 // diag (optional, [P][N]) receives the diagonal of the unnormalised A
 pl_status launch_coherence(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
                            int prec, float2* coh, float* diag, hipStream_t s);
-pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int method,
-                            float2* phasors, float* phase, float* lambda, uint8_t* flags,
-                            unsigned long long* counters, hipStream_t s);
+// output rows [oy_lo, oy_hi) only, optionally as packed upper triangles
+pl_status launch_coherence_rows(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
+                                int prec, float2* coh, int packed, int64_t oy_lo, int64_t oy_hi,
+                                hipStream_t s);
+pl_status launch_coherence_args(CohArgs& a, int prec, hipStream_t s);  // a: t, N, g, mask, coh, diag,
+                                                                       // packed, oy_lo, oy_hi set
+pl_status launch_phase_link(const LinkArgs& a, hipStream_t s);
+LinkArgs link_args(const float2* coh, int N, int64_t npix, int ref, int method, float2* phasors,
+                   float* phase, float* lambda, uint8_t* flags, unsigned long long* counters);
 // adjoint of coherence + linking: per-pixel S = Abar + Abar^H (upper
 // triangle, entry-major [N(N+1)/2][P]) from the recomputed coherence, then
 // grad z_q = sum over the windows holding q as an SHP of S_p z_q
@@ -127,7 +140,7 @@ pl_status launch_link_vjp(const float2* coh, const float* diag, const uint8_t* f
 pl_status launch_vjp_gather(const PlaneTable& t, int N, const Geometry& g, const uint32_t* mask,
                             const float2* S, float2* grad, hipStream_t s);
 pl_status launch_compress(const PlaneTable& t, int N, int first_real, const Geometry& g,
-                          const float2* phasors, float2* kappa, hipStream_t s);
+                          const float2* phasors, float2* kappa, hipStream_t s, int rot = -1);
 
 // ---- argument set-up and batched (persistent, multi-item) launches
 bool stats_args(const PlaneTable& t, int first, int M, int64_t npix, double* mean, double* var,

@@ -23,6 +23,14 @@
 //     the inertia check accepts one); this keeps the iteration count low when
 //     the eigen-gap is small compared with the distance from 0.99.
 //  4. zeta_i = x_i conj(x_ref), returned as unit phasors.
+//  5. Optionally the temporal coherence of the result (Sec. 3.3,
+//     eq. temporal-coherence): gamma_t = |sum_{i<k} u(C_ik) conj(zeta_i)
+//     zeta_k| / (N(N-1)/2), u(c) = c / |c| (1 for c = 0), from C's upper
+//     triangle re-read from cache and zeta broadcast between the lanes.
+//
+// C arrives either as full matrices or as packed upper triangles (row-major
+// entries (i, j >= i)); with the packed layout every row reads the Hermitian
+// matrix of the upper triangle.
 #include <cmath>
 #include <utility>
 
@@ -32,7 +40,10 @@
 namespace plk {
 namespace {
 
-
+// offset of entry (i, j), i <= j, inside one pixel's matrix
+__device__ __forceinline__ int centry(int packed, int N, int i, int j) {
+    return packed ? ((i * (2 * N - i - 1)) >> 1) + j : i * N + j;
+}
 
 template <int R, int NJ>
 __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
@@ -65,10 +76,11 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     // Loads are issued for every slot at clamped, in-bounds addresses and the
     // values selected afterwards: a load inside a per-entry branch waits for
     // its data before the next one is issued.
-    const float2* mat = a.coh + (active ? pix : 0) * (int64_t)(N * N);
-    const float2* src = mat + (int64_t)min(l, N - 1) * N;  // row l (clamped)
+    const int packed = a.packed;
+    const float2* mat = a.coh + (active ? pix : 0) * (int64_t)(packed ? (N * (N + 1)) >> 1 : N * N);
+    const float2* src = mat + (int64_t)min(l, N - 1) * N;  // row l (clamped), full layout
     float2 c[R][NJ];
-    if constexpr (R == 1) {
+    if (R == 1 && !packed) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             const float2 v = src[min(j, N - 1)];
@@ -84,7 +96,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 const int jc = min(j, N - 1);
-                float2 v = mat[min(i, jc) * N + max(i, jc)];  // entry (min, max): no branch
+                float2 v = mat[centry(packed, N, min(i, jc), max(i, jc))];  // entry (min, max): no branch
                 v.y = jc < i ? -v.y : v.y;
                 c[r][j] = (live[r] && j < N) ? v : make_float2(0.f, 0.f);
             }
@@ -164,10 +176,19 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     if constexpr (R == 1) {
         // row i of C is read again (an L2 hit) rather than kept live across step 1
         const float2* src2 = src + opaque_int(0);
+        const float2* mat2 = mat + opaque_int(0);
+        const int i0 = min(l, N - 1);
         float2* bme = lds + threadIdx.x;  // element j at bme[j * kBlock]
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const float2 cl = src2[min(j, N - 1)];
+            float2 cl;
+            if (!packed) {
+                cl = src2[min(j, N - 1)];
+            } else {
+                const int jc = min(j, N - 1);
+                cl = mat2[centry(1, N, min(i0, jc), max(i0, jc))];
+                cl.y = jc < i0 ? -cl.y : cl.y;
+            }
             const float2 cj = (live[0] && j < N) ? cl : make_float2(0.f, 0.f);
             const float2 v = use_evd ? make_float2(-cj.x, -cj.y)
                                      : make_float2((float)gi[0][j] * cj.x, (float)gi[0][j] * cj.y);
@@ -253,22 +274,62 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
         if (a.ref >= 16 * r) xs = x[r];
     const int src_lane = grp * 16 + (a.ref & 15);
     const float2 xr = make_float2(__shfl(xs.x, src_lane, 64), __shfl(xs.y, src_lane, 64));
+    float2 phv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = l + 16 * r;
         float2 z = make_float2(x[r].x * xr.x + x[r].y * xr.y, x[r].y * xr.x - x[r].x * xr.y);  // x conj(x_ref)
         const float z2 = z.x * z.x + z.y * z.y;
         const float zi = __builtin_amdgcn_rsqf(z2);
-        float2 phv = (z2 > 0.f && !invalid) ? make_float2(z.x * zi, z.y * zi) : make_float2(1.f, 0.f);
-        if (i == a.ref) phv = make_float2(1.f, 0.f);
-        if (live[r]) a.ph[(int64_t)i * a.npix + pix] = phv;
+        phv[r] = (z2 > 0.f && !invalid) ? make_float2(z.x * zi, z.y * zi) : make_float2(1.f, 0.f);
+        if (i == a.ref) phv[r] = make_float2(1.f, 0.f);
+        if (live[r]) a.ph[(int64_t)i * a.ostride + pix] = phv[r];
         if (live[r] && a.phase)
-            a.phase[(int64_t)i * a.npix + pix] = (i == a.ref || invalid) ? 0.f : atan2f(phv.y, phv.x);
+            a.phase[(int64_t)i * a.ostride + pix] = (i == a.ref || invalid) ? 0.f : atan2f(phv[r].y, phv[r].x);
     }
     const uint8_t flag = invalid ? PL_FLAG_INVALID : (use_evd ? PL_FLAG_EVD : PL_FLAG_EMI);
     if (active && l == 0) {
         if (a.lam) a.lam[pix] = invalid ? __builtin_nanf("") : (use_evd ? -rho : rho);
         if (a.flags) a.flags[pix] = flag;
+    }
+    if (a.tcoh) {
+        // ---- 5. temporal coherence: row i contributes
+        // conj(zeta_i) sum_{k > i} u(C_ik) zeta_k; zeta_k comes from lane k % 16
+        // (slot k / 16) by DPP broadcast, in uniform control flow
+        const float2* mat3 = mat + opaque_int(0);
+        float sre = 0.f, sim = 0.f;
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            float2 acc[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = make_float2(0.f, 0.f);
+            auto one = [&](auto kc) __attribute__((always_inline)) {
+                constexpr int k = decltype(kc)::value;
+                const float zx = rowcast<k % 16>(phv[k / 16].x), zy = rowcast<k % 16>(phv[k / 16].y);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = l + 16 * r;
+                    const bool use = live[r] && k > i && k < N;
+                    const float2 cv = mat3[centry(packed, N, min(i, N - 1), min(k, N - 1))];
+                    const float c2 = cv.x * cv.x + cv.y * cv.y;
+                    const float q = __builtin_amdgcn_rsqf(c2);
+                    const float2 u = c2 > 0.f ? make_float2(cv.x * q, cv.y * q) : make_float2(1.f, 0.f);
+                    acc[r].x += use ? u.x * zx - u.y * zy : 0.f;
+                    acc[r].y += use ? u.x * zy + u.y * zx : 0.f;
+                }
+            };
+            (one(std::integral_constant<int, K>{}), ...);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {  // conj(zeta_i) acc
+                sre += phv[r].x * acc[r].x + phv[r].y * acc[r].y;
+                sim += phv[r].x * acc[r].y - phv[r].y * acc[r].x;
+            }
+        }(std::make_integer_sequence<int, NJ>{});
+        sre = gsum<16>(sre);
+        sim = gsum<16>(sim);
+        const float nifg = 0.5f * (float)N * (float)(N - 1);
+        float gt = N > 1 ? __builtin_sqrtf(sre * sre + sim * sim) / nifg : 1.f;
+        if (invalid) gt = 0.f;
+        if (active && l == 0) a.tcoh[pix] = gt;
     }
     if (a.counters) {
         const bool lead = active && l == 0;
@@ -283,6 +344,13 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
             if (nc) atomicAdd(a.counters + PL_CNT_NOT_CONVERGED, (unsigned long long)__popcll(nc));
             if (rt) atomicAdd(a.counters + PL_CNT_SHIFT_RETRY, (unsigned long long)rt);
             if (its) atomicAdd(a.counters + PL_CNT_ITERS, (unsigned long long)its);
+        }
+        // histogram of iterations per pixel (bin 15: 15 or more)
+        const int bin = it < 15 ? it : 15;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const uint64_t hb = __ballot(lead && !invalid && bin == b);
+            if (lane == 0 && hb) atomicAdd(a.counters + PL_CNT_ITER_HIST + b, (unsigned long long)__popcll(hb));
         }
     }
 }
@@ -349,12 +417,15 @@ pl_status launch_persistent(const LinkArgs& a, int64_t blocks, hipStream_t s) {
     return launch_ok("phase linking kernel");
 }
 
-pl_status launch_phase_link(const float2* coh, int N, int64_t npix, int ref, int method,
-                            float2* phasors, float* phase, float* lambda, uint8_t* flags,
-                            unsigned long long* counters, hipStream_t s) {
-    LinkArgs a{coh, N, npix, ref, method, phasors, phase, lambda, flags, counters};
-    const int64_t blocks = link_blocks(N, npix);
-    switch ((N + 3) / 4) {  // columns per row: N rounded up to a multiple of 4
+LinkArgs link_args(const float2* coh, int N, int64_t npix, int ref, int method, float2* phasors,
+                   float* phase, float* lambda, uint8_t* flags, unsigned long long* counters) {
+    LinkArgs a{coh, N, npix, ref, method, phasors, phase, lambda, flags, counters, nullptr, 0, npix};
+    return a;
+}
+
+pl_status launch_phase_link(const LinkArgs& a, hipStream_t s) {
+    const int64_t blocks = link_blocks(a.N, a.npix);
+    switch ((a.N + 3) / 4) {  // columns per row: N rounded up to a multiple of 4
         case 1: case 2: case 3: return launch_persistent<1, 12>(a, blocks, s);
         case 4: return launch_persistent<1, 16>(a, blocks, s);
         case 5: return launch_persistent<2, 20>(a, blocks, s);

@@ -3,6 +3,7 @@
 // is the ring of the K_max most recent compressed SLCs and the ring of the
 // K_max + 1 most recent per-mini-stack amplitude statistics (the ancillary
 // products stored with each compressed SLC, Sec. 3.1).
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -37,6 +38,8 @@ struct CkptHeader {
     int32_t M, K_max;
     pl_window w;
     int64_t count;
+    int32_t reference, pad;
+    double weight_decay;
 };
 
 template <class T>
@@ -79,6 +82,10 @@ pl_status pl_seq_create(const pl_seq_params* params, pl_seq** out) {
         return fail(PL_ERR_INVALID_ARG, "pl_seq_create: unknown precision");
     if (p.method != PL_LINK_EMI && p.method != PL_LINK_EVD)
         return fail(PL_ERR_INVALID_ARG, "pl_seq_create: unknown method");
+    if (p.reference != PL_SEQ_REF_COMPRESSED && p.reference != PL_SEQ_REF_LAST)
+        return fail(PL_ERR_INVALID_ARG, "pl_seq_create: unknown reference mode");
+    if (!(p.weight_decay > 0 && p.weight_decay <= 1))
+        return fail(PL_ERR_INVALID_ARG, "pl_seq_create: weight_decay outside (0, 1]");
     pl_seq* s = new (std::nothrow) pl_seq();
     if (!s) return fail(PL_ERR_WORKSPACE, "pl_seq_create: out of host memory");
     s->p = p;
@@ -137,20 +144,22 @@ pl_status pl_seq_push(pl_seq* s, const pl_c64* new_slcs, pl_c64* phasors_out, pl
     PlaneTable tn = contiguous_planes(new_slcs, M, plane);
     pl_status r = launch_amp_stats(tn, 0, M, plane, s->means + slot * plane, s->vars + slot * plane, st);
     if (r != PL_OK) return r;
-    // merge the statistics of mini-stacks k-K..k (weights M each)
+    // merge the statistics of mini-stacks k-K..k, weights M decay^age
     const double* mp[64];
     const double* vp[64];
     double w[64];
     const int G = K + 1;
+    double n_eff = 0.0;
     for (int j = 0; j < G; ++j) {
         const int sl = (int)((k - K + j) % (Kmax + 1));
         mp[j] = s->means + sl * plane;
         vp[j] = s->vars + sl * plane;
-        w[j] = (double)M;
+        w[j] = (double)M * std::pow(p.weight_decay, (double)(G - 1 - j));
+        n_eff += w[j];
     }
     r = launch_merge_stats(mp, vp, w, G, plane, s->mean_m, s->var_m, st);
     if (r != PL_OK) return r;
-    r = launch_shp_select(s->mean_m, s->var_m, s->g, (double)G * M, p.alpha, s->mask, s->cnt, cnt, st);
+    r = launch_shp_select(s->mean_m, s->var_m, s->g, n_eff, p.alpha, s->mask, s->cnt, cnt, st);
     if (r != PL_OK) return r;
     // stack = [kappa_{k-K} .. kappa_{k-1} | new], no copies
     PlaneTable t{};
@@ -159,13 +168,16 @@ pl_status pl_seq_push(pl_seq* s, const pl_c64* new_slcs, pl_c64* phasors_out, pl
     r = launch_coherence(t, N, s->g, s->mask, p.precision, s->coh, nullptr, st);
     if (r != PL_OK) return r;
     const int ref = K > 0 ? K - 1 : 0;  // the most recent compressed SLC
-    r = launch_phase_link(s->coh, N, s->opix, ref, p.method, s->phasors, nullptr, nullptr, s->flags, cnt, st);
+    r = launch_phase_link(link_args(s->coh, N, s->opix, ref, p.method, s->phasors, nullptr, nullptr, s->flags, cnt),
+                          st);
     if (r != PL_OK) return r;
     // new compressed SLC over the real images; it replaces the oldest ring
     // entry, which the kernels above have already consumed (stream order)
     float2* knew = Kmax > 0 ? s->kappa + (k % Kmax) * plane : reinterpret_cast<float2*>(kappa_out);
     if (knew) {
-        r = launch_compress(t, N, K, s->g, s->phasors, knew, st);
+        // PL_SEQ_REF_LAST: phasors re-referenced to the last real image,
+        // kappa = sum conj(zeta_i conj(zeta_last)) z_i = zeta_last kappa
+        r = launch_compress(t, N, K, s->g, s->phasors, knew, st, p.reference == PL_SEQ_REF_LAST ? N - 1 : -1);
         if (r != PL_OK) return r;
     }
     r = hip_ok(hipMemcpyAsync(phasors_out, s->phasors + (int64_t)K * s->opix,
@@ -186,6 +198,14 @@ pl_status pl_seq_push(pl_seq* s, const pl_c64* new_slcs, pl_c64* phasors_out, pl
     return PL_OK;
 }
 
+pl_status pl_seq_last_mask(const pl_seq* s, uint32_t* mask, pl_stream stream) {
+    if (!s || !mask) return fail(PL_ERR_INVALID_ARG, "pl_seq_last_mask: NULL pointer");
+    if (s->count == 0) return fail(PL_ERR_STATE, "pl_seq_last_mask: no mini-stack pushed yet");
+    return hip_ok(hipMemcpyAsync(mask, s->mask, (size_t)s->opix * s->g.nw * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                 reinterpret_cast<hipStream_t>(stream)),
+                  "pl_seq_last_mask: copy");
+}
+
 pl_status pl_seq_state_size(const pl_seq* s, size_t* bytes) {
     if (!s || !bytes) return fail(PL_ERR_INVALID_ARG, "pl_seq_state_size: NULL pointer");
     *bytes = state_bytes(s);
@@ -196,7 +216,8 @@ pl_status pl_seq_save(const pl_seq* s, void* host_buf, size_t bytes, pl_stream s
     if (!s || !host_buf) return fail(PL_ERR_INVALID_ARG, "pl_seq_save: NULL pointer");
     if (bytes < state_bytes(s)) return fail(PL_ERR_WORKSPACE, "pl_seq_save: buffer too small");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    CkptHeader h{kMagic, s->p.R, s->p.C, s->p.M, s->p.K_max, s->p.w, s->count};
+    CkptHeader h{kMagic, s->p.R, s->p.C, s->p.M, s->p.K_max, s->p.w, s->count, s->p.reference, 0,
+                 s->p.weight_decay};
     unsigned char* b = static_cast<unsigned char*>(host_buf);
     std::memcpy(b, &h, sizeof h);
     size_t off = sizeof h;
@@ -219,7 +240,8 @@ pl_status pl_seq_load(pl_seq* s, const void* host_buf, size_t bytes, pl_stream s
     const unsigned char* b = static_cast<const unsigned char*>(host_buf);
     std::memcpy(&h, b, sizeof h);
     if (h.magic != kMagic || h.R != s->p.R || h.C != s->p.C || h.M != s->p.M || h.K_max != s->p.K_max ||
-        std::memcmp(&h.w, &s->p.w, sizeof h.w) != 0 || h.count < 0)
+        std::memcmp(&h.w, &s->p.w, sizeof h.w) != 0 || h.count < 0 || h.reference != s->p.reference ||
+        h.weight_decay != s->p.weight_decay)
         return fail(PL_ERR_STATE, "pl_seq_load: checkpoint does not match this driver");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     size_t off = sizeof h;

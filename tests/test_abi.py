@@ -66,8 +66,8 @@ def test_argument_errors_return_before_any_device_work(lib):
     assert lib.pl_shp_select(fake, fake, 8, 8, 10.0, _w(1, 1, 1, 1), 1e-3, None, fake, None, None) == 1
     # N outside 1..32
     assert lib.pl_estimate_coherence(fake, 33, 8, 8, _w(1, 1, 1, 1), fake, 0, fake, None) == 3
-    assert lib.pl_phase_link(fake, 0, 10, 0, 0, fake, None, None, None, None, None) == 3
-    assert lib.pl_phase_link(None, 5, 0, 0, 0, None, None, None, None, None, None) == 0
+    assert lib.pl_phase_link(fake, 0, 10, 0, 0, fake, None, None, None, None, None, None) == 3
+    assert lib.pl_phase_link(None, 5, 0, 0, 0, None, None, None, None, None, None, None) == 0
     assert lib.pl_amplitude_stats(fake, 40, 4, 4, fake, fake, None) == 3
     # bad window / shapes
     assert lib.pl_shp_select(fake, fake, 8, 8, 10.0, _w(-1, 1, 1, 1), 1e-3, fake, fake, None, None) == 2
@@ -75,8 +75,8 @@ def test_argument_errors_return_before_any_device_work(lib):
     # bad scalars
     assert lib.pl_shp_select(fake, fake, 8, 8, 0.0, _w(1, 1, 1, 1), 1e-3, fake, fake, None, None) == 1
     assert lib.pl_shp_select(fake, fake, 8, 8, 5.0, _w(1, 1, 1, 1), 1.5, fake, fake, None, None) == 1
-    assert lib.pl_phase_link(fake, 5, 10, 5, 0, fake, None, None, None, None, None) == 1
-    assert lib.pl_phase_link(fake, 5, 10, 0, 7, fake, None, None, None, None, None) == 1
+    assert lib.pl_phase_link(fake, 5, 10, 5, 0, fake, None, None, None, None, None, None) == 1
+    assert lib.pl_phase_link(fake, 5, 10, 0, 7, fake, None, None, None, None, None, None) == 1
     assert lib.pl_estimate_coherence(fake, 5, 8, 8, _w(1, 1, 1, 1), fake, 9, fake, None) == 1
     assert lib.pl_compress_ministack(fake, 5, 5, 8, 8, _w(1, 1, 1, 1), fake, fake, None) == 1
     # adjoint: workspace size, too-small workspace, bad reference
@@ -94,8 +94,22 @@ def test_argument_errors_return_before_any_device_work(lib):
                                  n.value, None) == 1
     w = (ctypes.c_double * 2)(1.0, -1.0)
     assert lib.pl_merge_amplitude_stats(fake, fake, w, 2, 4, 4, fake, fake, None) == 1
+    # fused coherence + linking: one output row of packed matrices at least
+    lo, hi = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.pl_phase_link_fused_workspace(25, 96, 384, _w(11, 5, 6, 3), ctypes.byref(lo), ctypes.byref(hi)) == 0
+    assert lo.value == 64 * 325 * 8 and hi.value == 32 * lo.value
+    args = [fake, 25, 96, 384, _w(11, 5, 6, 3), fake, 1, 9, 0, fake, None, None, None, None, None, fake]
+    assert lib.pl_phase_link_fused(*args, lo.value - 1, None) == 5
+    assert lib.pl_phase_link_fused(*args[:15], None, lo.value, None) == 1
+    bad = list(args)
+    bad[7] = 25  # reference outside 0..N-1
+    assert lib.pl_phase_link_fused(*bad, lo.value, None) == 1
+    bad = list(args)
+    bad[1] = 33
+    assert lib.pl_phase_link_fused(*bad, lo.value, None) == 3
+    assert lib.pl_sync_report(None, None, None) == 1
     # empty pixel list is a no-op
-    assert lib.pl_phase_link(fake, 5, 0, 0, 0, fake, None, None, None, None, None) == 0
+    assert lib.pl_phase_link(fake, 5, 0, 0, 0, fake, None, None, None, None, None, None) == 0
     assert "ref_idx" in lib.pl_last_error().decode() or lib.pl_last_error() is not None
 
 
@@ -105,7 +119,32 @@ def test_sequential_parameter_checks(lib):
     assert lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)) == 3
     p = plink._SeqParams(64, 64, 15, 6, _w(2, 2, 1, 1), 2.0, 0, 0)
     assert lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)) == 1
+    p = plink._SeqParams(64, 64, 15, 6, _w(2, 2, 1, 1), 1e-3, 0, 0, 2)  # unknown reference mode
+    assert lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)) == 1
+    for decay in (0.0, 1.5, float("nan")):
+        p = plink._SeqParams(64, 64, 15, 6, _w(2, 2, 1, 1), 1e-3, 0, 0, 1, decay)
+        assert lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)) == 1
     assert lib.pl_seq_destroy(None) == 0
+
+
+def test_product_argument_checks(lib):
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    n = ctypes.c_int32()
+    assert lib.pl_network_size(15, 3, ctypes.byref(n)) == 0 and n.value == 39
+    assert lib.pl_network_size(32, 3, ctypes.byref(n)) == 0 and n.value == 90
+    assert lib.pl_network_size(15, 4, ctypes.byref(n)) == 3
+    assert lib.pl_network_size(1, 3, ctypes.byref(n)) == 3
+    assert lib.pl_network_invert_l1(fake, 15, 3, 100, 0.0, 10, fake, None, None) == 1  # rho
+    assert lib.pl_network_invert_l1(fake, 15, 3, 100, 1.0, -1, fake, None, None) == 1  # iterations
+    assert lib.pl_network_invert_l1(None, 15, 3, 0, 1.0, 10, None, None, None) == 0   # no pixels
+    assert lib.pl_phase_similarity(fake, 15, 10, 10, None, 16, 3, fake, None) == 3      # radius
+    assert lib.pl_phase_similarity(fake, 15, 10, 10, None, 3, 4, fake, None) == 3       # network
+    assert lib.pl_phase_similarity(None, 15, 10, 10, None, 3, 3, fake, None) == 1
+    w = _w(11, 5, 6, 3)
+    assert lib.pl_ps_regrid(fake, 15, 96, 384, w, 15, fake, fake, 0.2, fake, fake, None, None, None) == 1
+    assert lib.pl_ps_regrid(fake, 15, 96, 384, w, 0, fake, fake, -0.2, fake, fake, None, None, None) == 1
+    assert lib.pl_ps_regrid(fake, 15, 96, 384, w, 0, None, fake, 0.2, fake, fake, None, None, None) == 1
 
 
 def test_binding_refuses_cpu_tensors():

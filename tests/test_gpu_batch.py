@@ -106,7 +106,7 @@ def test_batch_items_against_oracle(gpu_lib, prec):
         ph = b.phasors[i].cpu().numpy().reshape(wl.N, -1)
         err = phase_errors(ph, r["link"]["phasor"])
         check_phases(f"batch item {i} (N={wl.N}, {wl.R}x{wl.C})", err, sensitivity(r["coh"], ref),
-                     b.flags[i].cpu().numpy(), r["link"], prec, dC_pix=dC, min_well_posed=len(dC) // 2)
+                     b.flags[i].cpu().numpy(), r["link"], prec, r["coh"], dC_pix=dC, min_well_posed=len(dC) // 10)
         kap = O.compress(z.cpu().numpy(), wl.n_comp, b.phasors[i].cpu().numpy(), wl.window)
         scale = np.abs(z[wl.n_comp:].cpu().numpy()).astype(np.float64).sum(0)
         assert np.max(np.abs(b.kappa[i].cpu().numpy() - kap) / scale) <= 1e-6

@@ -120,7 +120,7 @@ def _check(wl, z, ref, samples, out, precisions):
         assert dmax <= min(COH_TOL, EPS[prec])
         err = phase_errors(out[prec]["ph"][:, keep], link["phasor"])
         check_phases(f"{wl.name} full size, {len(keep)} samples", err, sens, out[prec]["flags"][keep], link,
-                     prec, dC_pix=dC, min_well_posed=len(keep) // 2)
+                     prec, Co_all, dC_pix=dC, min_well_posed=len(keep) // 10)
 
 
 def _check_kappa(wl, z, out, prec, rng):
@@ -216,4 +216,4 @@ def test_large_crop_every_pixel(gpu_lib, name, R, C, seed):
         link = {k: orc["link"][k][..., keep] for k in ("flag", "min_pivot", "phasor")}
         err = phase_errors(ph.cpu().numpy()[:, keep], link["phasor"])
         check_phases(f"{name} {R}x{C} crop", err, sens[keep], flags.cpu().numpy()[keep], link, prec,
-                     dC_pix=dC, min_well_posed=int(keep.sum()) // 2)
+                     orc["coh"][keep], dC_pix=dC, min_well_posed=int(keep.sum()) // 10)

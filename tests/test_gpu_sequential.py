@@ -83,7 +83,7 @@ def test_sequential_teacher_forced(gpu_lib, prec):
         np.testing.assert_array_equal(link["phasor"][nc:], o["phasor"].reshape(M, -1))
         err = phase_errors(ph.cpu().numpy(), link["phasor"])
         check_phases(f"teacher-forced mini-stack {k} (N={M + nc})", err, sens, fl.cpu().numpy(), link, prec,
-                     dC_pix=dC, min_well_posed=len(sens) // 2)
+                     o["coh"], dC_pix=dC, min_well_posed=len(sens) // 10)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
