@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--only-main", action="store_true",
                     help="skip the other-workload, batched-sequence and adjoint legs")
+    ap.add_argument("--skip-fused", action="store_true", help="do not time the fused coherence + linking step")
     ap.add_argument("--cpu-workers", type=int, default=0,
                     help="oracle worker processes (default: the usable host cores, at most 16)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -335,7 +336,7 @@ def accuracy_vs_oracle(torch, plink, wl, z, orc):
     return out
 
 
-def measure(torch, plink, wl, stack, prec, steps, warmup):
+def measure(torch, plink, wl, stack, prec, steps, warmup, skip_fused=False):
     """ms/step (median), per-stage ms, solver counters and SHP total of the
     single-call path at one precision."""
     import numpy as np
@@ -355,6 +356,13 @@ def measure(torch, plink, wl, stack, prec, steps, warmup):
     del m, coh, ln, k
     print(f"[bench] {wl.name} {prec}: {t['median']:.3f} ms/step (median), stages "
           f"{json.dumps({k: round(v, 4) for k, v in stages.items()})}", file=sys.stderr, flush=True)
+    if skip_fused:
+        return {"ms": t["median"], "ms_mean": t["mean"], "ms_min": t["min"], "ms_max": t["max"], "stages": stages,
+                "fused": None, "shp_sum": shp_sum, "value": P / (t["median"] * 1e-3),
+                "evd_frac": float(np.mean(flags == 1)), "invalid_frac": float(np.mean(flags == 2)),
+                "link_counters": {"iters_per_pixel": cnt["iters"] / P,
+                                  "shift_retries_per_pixel": cnt["shift_retry"] / P,
+                                  "not_converged": cnt["not_converged"], "glrt_band_pairs": cnt["glrt_band"]}}
     # the same step with coherence and linking fused through a bounded buffer
     # of packed coherence bands (at most 1 GiB, whole rows)
     row, full = plink.phase_link_fused_workspace(wl.N, wl.R, wl.C, wl.window)
@@ -405,7 +413,7 @@ def leg_other(torch, plink, synth, args, name, steps, warmup):
     stack = synth.make_stack(wl, seed=args.seed, device="cuda")
     out = {"workload": describe(wl)}
     for prec in ("fp32", "bf16"):
-        r = measure(torch, plink, wl, stack, prec, steps, warmup)
+        r = measure(torch, plink, wl, stack, prec, steps, warmup, args.skip_fused)
         _, sr = stage_rooflines(wl, r, prec)
         out[prec] = {"value": r["value"], "unit": "pixels/s", "ms_per_step": r["ms"], "ms_per_step_mean": r["ms_mean"],
                      "stage_ms": {k: round(v, 4) for k, v in r["stages"].items()}, "stage_roofline": sr,
@@ -482,8 +490,11 @@ def leg_adjoint(torch, plink, synth, args):
     flags = state["r"][2]
     ms_f = time_steps(torch, fwd, 10, 3)["median"]
     ms_b = time_steps(torch, lambda: plink.phase_link_vjp(z, mask, flags, wl.window, 0, g, workspace=ws), 10, 3)["median"]
+    del ws
+    ms_b64 = time_steps(torch, lambda: plink.phase_link_vjp(z, mask, flags, wl.window, 0, g, precision="fp64"),
+                        3, 1)["median"]
     return {"workload": f"{wl.R}x{wl.C}, N={wl.N}, half-window {wl.window[0]}x{wl.window[1]}, stride 1",
-            "forward_ms": ms_f, "vjp_ms": ms_b, "unit": "ms"}
+            "forward_ms": ms_f, "vjp_ms": ms_b, "vjp_fp64_ms": ms_b64, "unit": "ms"}
 
 
 def main():
@@ -519,7 +530,7 @@ def main():
     results = {}
     precs = [args.precision] + ([] if args.no_compare else [p for p in ("bf16", "fp32") if p != args.precision])
     for prec in precs:
-        results[prec] = measure(torch, plink, wl, stack, prec, args.steps, args.warmup)
+        results[prec] = measure(torch, plink, wl, stack, prec, args.steps, args.warmup, args.skip_fused)
     del stack
     torch.cuda.empty_cache()
 

@@ -228,6 +228,22 @@ pl_status pl_phase_link_vjp(const pl_c64* stack, int32_t N, int64_t R, int64_t C
                             pl_precision prec, const float* grad_phase, pl_c64* grad_stack,
                             void* workspace, size_t ws_bytes, pl_stream stream);
 
+/* The same vector-Jacobian product with every step in FP64: the sample
+ * coherence accumulated in FP64 from the complex64 stack (each product of two
+ * FP32 values is exact in FP64), |C| inverted and the eigenpair of
+ * |C|^-1 o C (or -C) found by shifted inverse iteration in FP64, and the
+ * pseudo-inverse solve, Gbar and the gather in FP64; grad_stack is rounded
+ * to complex64 at the end.  Meant for derivatives that must match finite
+ * differences of an FP64 evaluation (the FP32 call is limited by the FP32
+ * eigen-solve).  flags hold the EMI/EVD choice fixed as above; an EMI pixel
+ * whose |C| has an LDL^T pivot <= 1e-6 in FP64 contributes nothing.
+ * workspace: at least pl_phase_link_vjp64_workspace() bytes
+ * (N(N+1)/2 * oR*oC * 16).  Errors as pl_phase_link_vjp. */
+pl_status pl_phase_link_vjp64_workspace(int32_t N, int64_t R, int64_t C, pl_window w, size_t* bytes);
+pl_status pl_phase_link_vjp64(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                              const uint32_t* mask, const uint8_t* flags, int32_t ref_idx, const float* grad_phase,
+                              pl_c64* grad_stack, void* workspace, size_t ws_bytes, pl_stream stream);
+
 /* ------------------------------------------------------ compressed SLC
  * Compressed SLC of a mini-stack (Sec. 2.2): kappa = zeta^H z over the real
  * images first_real..N-1, i.e. kappa(p) = sum_i conj(zeta_i(b(p))) z_i(p),

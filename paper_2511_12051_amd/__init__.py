@@ -106,6 +106,9 @@ _SIGNATURES = {
     "pl_phase_link_vjp_workspace": (ctypes.c_int, [_I32, _I64, _I64, _Window, ctypes.POINTER(ctypes.c_size_t)]),
     "pl_phase_link_vjp": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, _P, _I32, ctypes.c_int, _P, _P,
                                          _P, ctypes.c_size_t, _P]),
+    "pl_phase_link_vjp64_workspace": (ctypes.c_int, [_I32, _I64, _I64, _Window, ctypes.POINTER(ctypes.c_size_t)]),
+    "pl_phase_link_vjp64": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, _P, _I32, _P, _P, _P,
+                                           ctypes.c_size_t, _P]),
     "pl_compress_ministack": (ctypes.c_int, [_P, _I32, _I32, _I64, _I64, _Window, _P, _P, _P]),
     "pl_batch_plan": (ctypes.c_int, [ctypes.POINTER(_BatchItem), _I32, _Window, _D, ctypes.c_int, ctypes.c_int,
                                      _I32, _P, ctypes.POINTER(_P)]),
@@ -390,7 +393,10 @@ def phase_link_vjp_workspace(N: int, R: int, C: int, window) -> int:
 def phase_link_vjp(stack: torch.Tensor, mask: torch.Tensor, flags: torch.Tensor, window, ref: int,
                    grad_phase: torch.Tensor, precision="fp32", workspace: torch.Tensor | None = None):
     """dL/dz (as dL/dRe + j dL/dIm, complex64 [N,R,C]) of the linked phases given
-    dL/dphi (float32 [N, oR*oC] or [N,oR,oC]); mask and EMI/EVD flags held fixed."""
+    dL/dphi (float32 [N, oR*oC] or [N,oR,oC]); mask and EMI/EVD flags held fixed.
+    precision "fp64" runs every step of the adjoint in double precision."""
+    if precision == "fp64":
+        return _phase_link_vjp64(stack, mask, flags, window, ref, grad_phase, workspace)
     _need(stack, torch.complex64, 3, "phase_link_vjp")
     _need(mask, torch.int32, 3, "phase_link_vjp mask")
     N, R, C = stack.shape
@@ -413,21 +419,46 @@ def phase_link_vjp(stack: torch.Tensor, mask: torch.Tensor, flags: torch.Tensor,
     return grad
 
 
+def _phase_link_vjp64(stack, mask, flags, window, ref, grad_phase, workspace=None):
+    _need(stack, torch.complex64, 3, "phase_link_vjp")
+    _need(mask, torch.int32, 3, "phase_link_vjp mask")
+    N, R, C = stack.shape
+    oR, oC = output_grid(R, C, window)
+    if tuple(mask.shape) != (oR, oC, mask_words(window)):
+        raise PlinkError("phase_link_vjp: mask shape does not match the window")
+    if flags.dtype != torch.uint8 or flags.numel() != oR * oC or not flags.is_contiguous():
+        raise PlinkError("phase_link_vjp: flags must be contiguous uint8 [oR*oC]")
+    if (grad_phase.dtype != torch.float32 or grad_phase.numel() != N * oR * oC
+            or not grad_phase.is_contiguous() or grad_phase.device != stack.device):
+        raise PlinkError("phase_link_vjp: grad_phase must be contiguous float32 [N, oR*oC] on the stack's GPU")
+    n = ctypes.c_size_t()
+    _check(load().pl_phase_link_vjp64_workspace(N, R, C, _win(window), ctypes.byref(n)), "phase_link_vjp64_workspace")
+    if workspace is None or workspace.numel() * workspace.element_size() < n.value:
+        workspace = torch.empty((n.value,), dtype=torch.uint8, device=stack.device)
+    grad = torch.empty_like(stack)
+    _check(load().pl_phase_link_vjp64(_ptr(stack), N, R, C, _win(window), _ptr(mask), _ptr(flags), int(ref),
+                                      _ptr(grad_phase), _ptr(grad), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(), _stream(stack)), "phase_link_vjp64")
+    return grad
+
+
 class PhaseLink(torch.autograd.Function):
     """Linked phases [N, oR, oC] of a stack [N, R, C] (complex64) for a fixed SHP
-    mask, differentiable with respect to the stack.  The forward is the fused
+    mask, differentiable with respect to the stack (backward_precision "fp64"
+    selects the FP64 adjoint; default: the forward's precision).  The forward is the fused
     coherence + linking entry point (no full-size coherence array); the
     backward recomputes the coherence and the eigen-solve inside the adjoint
     kernels (only the stack, the mask and the per-pixel EMI/EVD flags are
     kept)."""
 
     @staticmethod
-    def forward(ctx, stack, mask, window, ref=0, precision="fp32", method="emi"):
+    def forward(ctx, stack, mask, window, ref=0, precision="fp32", method="emi", backward_precision=None):
         N, R, C = stack.shape
         oR, oC = output_grid(R, C, window)
         _, _, flags, phase = phase_link_fused(stack, mask, window, ref, precision, method, want_phase=True)
         ctx.save_for_backward(stack, mask, flags)
-        ctx.window, ctx.ref, ctx.precision = tuple(window), int(ref), precision
+        ctx.window, ctx.ref = tuple(window), int(ref)
+        ctx.precision = backward_precision or precision
         ctx.mark_non_differentiable(flags)
         return phase.view(N, oR, oC), flags
 
@@ -436,7 +467,7 @@ class PhaseLink(torch.autograd.Function):
         stack, mask, flags = ctx.saved_tensors
         g = grad_phase.to(torch.float32).contiguous()
         grad = phase_link_vjp(stack, mask, flags, ctx.window, ctx.ref, g, ctx.precision)
-        return grad, None, None, None, None, None
+        return grad, None, None, None, None, None, None
 
 
 def compress_ministack(stack: torch.Tensor, first_real: int, window, phasors: torch.Tensor):

@@ -169,3 +169,130 @@ def test_autograd_function(gpu_lib):
     (phase * w).sum().backward()
     direct = plink.phase_link_vjp(z, mask, flags, wl.window, 2, w.reshape(wl.N, -1).contiguous())
     assert torch.equal(zz.grad, direct)
+
+
+# ---------------------------------------------------------------- FP64 adjoint
+def _fd_case():
+    from adjoint_fd import fd_gradient
+    wl = synth.crop("adjoint", 36, 36)
+    z = synth.make_stack(wl, seed=51)
+    zn = z.numpy().astype(np.complex128)
+    mean, var = O.amplitude_stats(zn)
+    mask, _, _ = O.shp_select(mean, var, wl.n_new, wl.window, wl.alpha)
+    Cm, valid = O.coherence(zn, mask, wl.window)
+    ref = 2
+    flags = O.phase_link(Cm, ref=ref, valid=valid)["flag"]
+    rng = np.random.default_rng(52)
+    g = rng.normal(size=(wl.N, len(flags)))
+    entries = [(int(rng.integers(wl.N)), int(rng.integers(wl.R)), int(rng.integers(wl.C))) for _ in range(64)]
+    fd = fd_gradient(zn, mask, wl.window, ref, flags, g, entries)
+    return wl, z, mask, flags, ref, g, entries, fd
+
+
+def test_vjp64_matches_finite_differences(gpu_lib):
+    """The differentiation configuration's shape (N = 20, half-window 7 x 7,
+    stride 1): the FP64 adjoint against FP64 central differences (h = 1e-6)
+    of the oracle at 64 random input pixels, to 1e-6 relative, and against
+    the oracle's adjoint element by element.  dL/dphi is rounded to FP32 (the
+    entry point's type) on both sides."""
+    plink = gpu_lib
+    wl, z, mask, flags, ref, g, entries, fd = _fd_case()
+    g32 = g.astype(np.float32)
+    # the differences above used g in FP64; recompute them with the FP32 values
+    from adjoint_fd import fd_gradient
+    fd = fd_gradient(z.numpy().astype(np.complex128), mask, wl.window, ref, flags, g32.astype(np.float64), entries)
+    grad = plink.phase_link_vjp(z.cuda(), torch.from_numpy(mask.view(np.int32)).cuda(),
+                                torch.from_numpy(flags).cuda(), wl.window, ref, torch.from_numpy(g32).cuda(),
+                                precision="fp64").cpu().numpy()
+    an = np.array([grad[n, y, x] for n, y, x in entries]).astype(np.complex128)
+    rel = np.linalg.norm(an - fd) / np.linalg.norm(fd)
+    want = O.phase_link_vjp(z.numpy(), mask, wl.window, ref, g32.astype(np.float64), flags)
+    d = np.abs(grad.astype(np.complex128) - want).max() / np.abs(want).max()
+    print(f"[adjoint] FP64 vs finite differences: {rel:.2e} relative; vs oracle adjoint {d:.2e} of max", flush=True)
+    assert rel <= 1e-6
+    assert d <= 1e-6  # the complex64 rounding of the output (6e-8) dominates
+
+
+def test_vjp64_full_size_phase_screen_and_samples(gpu_lib):
+    """512 x 512, N = 20: the phase-screen identity over the whole image to
+    1e-6 relative (the gradient is rounded to complex64), and sampled input
+    pixels against the oracle's adjoint on local crops with dL/dphi on every
+    pixel (no well-posed restriction is needed in FP64)."""
+    plink = gpu_lib
+    wl = synth.WORKLOADS["adjoint"]
+    hx, hy, sx, sy = wl.window
+    z = synth.make_stack(wl, seed=23, device="cuda")
+    ref = 0
+    mask, coh, ph, flags = _forward(plink, z, wl, ref, "emi")
+    P = wl.R * wl.C
+    rng = np.random.default_rng(8)
+    # dL/dphi on 4000 random pixels (an EMI pixel whose |C| stops inverting
+    # in FP64 would contribute nothing; on a random subset that is unlikely
+    # and would show as a failure)
+    g = np.zeros((wl.N, P), np.float32)
+    pick = rng.choice(P, 4000, replace=False)
+    g[:, pick] = rng.standard_normal((wl.N, 4000)).astype(np.float32)
+    grad = plink.phase_link_vjp(z, mask, flags, wl.window, ref, torch.from_numpy(g).cuda(), precision="fp64")
+    torch.cuda.synchronize()
+    c = -(torch.conj(grad.to(torch.complex128)) * z.to(torch.complex128)).imag.sum(dim=(1, 2)).cpu().numpy()
+    fl = flags.cpu().numpy()
+    gv = g.astype(np.float64) * (fl != O.FLAG_INVALID)[None]
+    want = gv.sum(axis=1)
+    want[ref] -= gv.sum()
+    scale = np.abs(gv).sum() / wl.N
+    err = np.abs(c - want).max()
+    print(f"[adjoint] FP64 phase screen, full size: max |c - want| {err:.3e}, scale {scale:.3e}", flush=True)
+    assert err <= 1e-6 * scale
+    g = rng.standard_normal((wl.N, P)).astype(np.float32)
+    grad = plink.phase_link_vjp(z, mask, flags, wl.window, ref, torch.from_numpy(g).cuda(), precision="fp64")
+    zc = z.cpu().numpy()
+    mask_np = mask.cpu().numpy().view(np.uint32)
+    flags_np = fl.reshape(wl.R, wl.C)
+    gg = g.reshape(wl.N, wl.R, wl.C)
+    grad = grad.cpu().numpy()
+    worst, scale = 0.0, 0.0
+    for qy, qx in [(0, 0), (wl.R - 1, wl.C - 1), (0, 300)] + [tuple(v) for v in rng.integers(0, [wl.R, wl.C], (5, 2))]:
+        y0, y1 = max(0, qy - 2 * hy), min(wl.R, qy + 2 * hy + 1)
+        x0, x1 = max(0, qx - 2 * hx), min(wl.C, qx + 2 * hx + 1)
+        o = O.phase_link_vjp(zc[:, y0:y1, x0:x1], mask_np[y0:y1, x0:x1], wl.window, ref,
+                             gg[:, y0:y1, x0:x1].reshape(wl.N, -1).astype(np.float64), flags_np[y0:y1, x0:x1].ravel())
+        worst = max(worst, np.abs(grad[:, qy, qx] - o[:, qy - y0, qx - x0]).max())
+        scale = max(scale, np.abs(o[:, qy - y0, qx - x0]).max())
+    print(f"[adjoint] FP64 sampled full size: max err {worst:.3e} of max |grad| {scale:.3e}", flush=True)
+    assert worst <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-7), ("fp32", 2e-3)])
+def test_uncertainty_propagation_per_slc_phase(gpu_lib, precision, tol):
+    """A 0.1-rad phase perturbation of each SLC (one value per image),
+    linearised through the adjoint: with J_in(p) = dphi_i(p) / d delta_n =
+    -sum_q Im(conj(dphi_i(p)/dz_n(q)) z_n(q)), std(phi_i) = 0.1 sqrt(sum_n J_in^2)
+    must be 0.1 sqrt(2) for i != ref and 0 at ref (phi_i moves by
+    delta_i - delta_ref exactly).  64 output pixels on a grid 64 pixels apart,
+    so that one adjoint call per image i (dL/dphi = 1 at the 64 pixels for
+    image i) gives every pixel's row of J from its own window region."""
+    plink = gpu_lib
+    wl = synth.WORKLOADS["adjoint"]
+    hx, hy, _, _ = wl.window
+    z = synth.make_stack(wl, seed=24, device="cuda")
+    ref = 3
+    mask, coh, ph, flags = _forward(plink, z, wl, ref, "emi")
+    pts = [(32 + 64 * a, 32 + 64 * b) for a in range(8) for b in range(8)]
+    fl = flags.cpu().numpy().reshape(wl.R, wl.C)
+    pts = [p for p in pts if fl[p] != O.FLAG_INVALID]
+    N = wl.N
+    J = np.zeros((len(pts), N, N))
+    for i in range(N):
+        g = torch.zeros((N, wl.R, wl.C), dtype=torch.float32, device="cuda")
+        for (y, x) in pts:
+            g[i, y, x] = 1.0
+        grad = plink.phase_link_vjp(z, mask, flags, wl.window, ref, g.reshape(N, -1), precision=precision)
+        prod = -(torch.conj(grad.to(torch.complex128)) * z.to(torch.complex128)).imag  # [N, R, C]
+        for k, (y, x) in enumerate(pts):
+            J[k, i] = prod[:, y - 2 * hy:y + 2 * hy + 1, x - 2 * hx:x + 2 * hx + 1].sum(dim=(1, 2)).cpu().numpy()
+    std = 0.1 * np.sqrt((J ** 2).sum(axis=2))  # [pixels, N]
+    want = np.full(N, 0.1 * np.sqrt(2.0))
+    want[ref] = 0.0
+    err = np.abs(std - want[None]).max()
+    print(f"[adjoint] {precision} uncertainty of {len(pts)} pixels: max |std - closed form| {err:.2e} rad", flush=True)
+    assert err <= tol

@@ -534,6 +534,29 @@ def test_adjoint_matches_central_finite_differences(method):
     assert np.linalg.norm(an - fd) <= 1e-6 * np.linalg.norm(fd)
 
 
+def test_adjoint_fd_at_the_differentiation_config():
+    """The differentiation configuration's shape (N = 20, half-window 7 x 7,
+    stride 1): the oracle's adjoint against FP64 central differences
+    (h = 1e-6) at 64 random input pixels (a random image each, both real and
+    imaginary parts), to 1e-6 relative."""
+    import synth
+    from adjoint_fd import fd_gradient
+    wl = synth.crop("adjoint", 36, 36)
+    z = synth.make_stack(wl, seed=51).numpy().astype(np.complex128)
+    mean, var = O.amplitude_stats(z)
+    mask, _, _ = O.shp_select(mean, var, wl.n_new, wl.window, wl.alpha)
+    Cm, valid = O.coherence(z, mask, wl.window)
+    ref = 2
+    flags = O.phase_link(Cm, ref=ref, valid=valid)["flag"]
+    rng = np.random.default_rng(52)
+    g = rng.normal(size=(wl.N, len(flags)))
+    grad = O.phase_link_vjp(z, mask, wl.window, ref, g, flags)
+    entries = [(int(rng.integers(wl.N)), int(rng.integers(wl.R)), int(rng.integers(wl.C))) for _ in range(64)]
+    fd = fd_gradient(z, mask, wl.window, ref, flags, g, entries)
+    an = np.array([grad[n, y, x] for n, y, x in entries])
+    assert np.linalg.norm(an - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
 def test_adjoint_phase_screen_closed_form():
     """z_i -> z_i exp(j d_i) moves phi_i by d_i - d_ref exactly, so the VJP
     contracted with dz = j d_i z_i equals sum_p sum_i g_i (d_i - d_ref)."""
