@@ -254,6 +254,19 @@ pl_status pl_compress_ministack(const pl_c64* stack, int32_t N, int32_t first_re
                                 int64_t C, pl_window w, const pl_c64* phasors, pl_c64* kappa,
                                 pl_stream stream);
 
+/* The same as pl_phase_link_fused for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the bands go through a library-owned 128 MiB device
+ * buffer, one per GPU, held until the process ends; the call allocates
+ * nothing.  Every call on one GPU uses that GPU's buffer, so calls that
+ * overlap on one GPU (other streams, other host threads) race: serialise
+ * them.  Errors: PL_ERR_WORKSPACE when one output row of packed coherence
+ * (oC * N(N+1)/2 * 8 bytes) exceeds the buffer. */
+pl_status pl_phase_link_fused_noalloc(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                                      const uint32_t* mask, pl_precision prec, int32_t ref_idx,
+                                      pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
+                                      float* temp_coh, uint8_t* flags, uint64_t* counters, pl_stream stream);
+
 /* -------------------------------------- products of the linked phases */
 
 /* Persistent scatterers and regridding to the output grid (Sec. 3.1: the

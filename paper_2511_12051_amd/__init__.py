@@ -99,6 +99,8 @@ _SIGNATURES = {
                                                      ctypes.POINTER(ctypes.c_size_t)]),
     "pl_phase_link_fused": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, ctypes.c_int, _I32, ctypes.c_int,
                                            _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "pl_phase_link_fused_noalloc": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _P, ctypes.c_int, _I32,
+                                                   ctypes.c_int, _P, _P, _P, _P, _P, _P, _P]),
     "pl_ps_regrid": (ctypes.c_int, [_P, _I32, _I64, _I64, _Window, _I32, _P, _P, _D, _P, _P, _P, _P, _P]),
     "pl_phase_similarity": (ctypes.c_int, [_P, _I32, _I64, _I64, _P, _I32, _I32, _P, _P]),
     "pl_network_size": (ctypes.c_int, [_I32, _I32, ctypes.POINTER(_I32)]),

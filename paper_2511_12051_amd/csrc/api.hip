@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -130,6 +131,36 @@ pl_status fused_check(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_w
 }
 }  // namespace
 }  // namespace plk
+
+// ---- the fused path without allocation: the band buffer is a file-scope
+// device array, one copy per GPU, whose device address is looked up once per
+// device (the array's name in host code is not a device address)
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace plk {
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+pl_status scratch_address(void** out) {
+    int dev = 0;
+    pl_status r = hip_ok(hipGetDevice(&dev), "pl_phase_link_fused_noalloc: current device");
+    if (r != PL_OK) return r;
+    if (dev < 0 || dev >= 64) return fail(PL_ERR_UNSUPPORTED, "pl_phase_link_fused_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        r = hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "pl_phase_link_fused_noalloc: scratch address");
+        if (r != PL_OK) return r;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PL_OK;
+}
+}  // namespace
+}  // namespace plk
+
 
 extern "C" {
 
@@ -268,6 +299,24 @@ pl_status pl_phase_link_fused_workspace(int32_t N, int64_t R, int64_t C, pl_wind
     return PL_OK;
 }
 
+
+pl_status pl_phase_link_fused_noalloc(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
+                                      const uint32_t* mask, pl_precision prec, int32_t ref_idx,
+                                      pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
+                                      float* temp_coh, uint8_t* flags, uint64_t* counters, pl_stream stream) {
+    Geometry g;
+    pl_status r =
+        fused_check(stack, N, R, C, w, mask, prec, ref_idx, method, phasors, "pl_phase_link_fused_noalloc", &g);
+    if (r != PL_OK) return r;
+    PL_CHECK(fused_row_bytes(N, g) <= kScratchBytes, PL_ERR_WORKSPACE,
+             "pl_phase_link_fused_noalloc: one output row needs %zu bytes of the %zu-byte scratch buffer",
+             fused_row_bytes(N, g), kScratchBytes);
+    void* ptr = nullptr;
+    r = scratch_address(&ptr);
+    if (r != PL_OK) return r;
+    return fused_run(stack, N, g, mask, prec, ref_idx, method, phasors, phase, lambda, temp_coh, flags, counters,
+                     static_cast<float2*>(ptr), kScratchBytes, S(stream));
+}
 
 pl_status pl_phase_link_fused(const pl_c64* stack, int32_t N, int64_t R, int64_t C, pl_window w,
                               const uint32_t* mask, pl_precision prec, int32_t ref_idx,
