@@ -343,7 +343,20 @@ typedef struct {
     double weight_decay; /* in (0, 1]; 1 = even weights */
 } pl_seq_params;
 
-/* Creates a driver; allocates its device state on the current device. */
+/* Bytes of device state a driver with these parameters needs (host call):
+ * the ring of K_max compressed SLCs, K_max + 1 per-mini-stack amplitude
+ * statistics and the merged ones, and the intermediates of one mini-stack
+ * (masks, counts, coherence, phasors, flags).  Errors as pl_seq_create. */
+pl_status pl_seq_workspace_size(const pl_seq_params* params, size_t* bytes);
+/* Creates a driver whose device state lives in the caller's buffer
+ * (device memory, 256-byte aligned, at least pl_seq_workspace_size bytes).
+ * The caller keeps ownership: the buffer must outlive the driver and is never
+ * freed by it; the driver allocates no device memory.  PL_ERR_WORKSPACE if
+ * the buffer is too small, PL_ERR_INVALID_ARG if it is NULL or misaligned. */
+pl_status pl_seq_create_in(const pl_seq_params* params, void* dev_workspace, size_t bytes, pl_seq** out);
+/* Creates a driver that allocates its device state (one block of
+ * pl_seq_workspace_size bytes) on the current device and frees it in
+ * pl_seq_destroy. */
 pl_status pl_seq_create(const pl_seq_params* params, pl_seq** out);
 pl_status pl_seq_destroy(pl_seq* s);
 /* Number of mini-stacks pushed so far (host). */

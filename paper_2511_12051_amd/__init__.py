@@ -118,6 +118,9 @@ _SIGNATURES = {
     "pl_batch_destroy": (ctypes.c_int, [_P]),
     "pl_batch_describe": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "pl_seq_create": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(_P)]),
+    "pl_seq_workspace_size": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "pl_seq_create_in": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.POINTER(_P)]),
     "pl_seq_destroy": (ctypes.c_int, [_P]),
     "pl_seq_count": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
     "pl_seq_push": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
@@ -603,7 +606,11 @@ class Sequential:
     exponentially less."""
 
     def __init__(self, R, C, M, K_max, window, alpha=1e-3, precision="fp32", method="emi",
-                 device="cuda", reference="compressed", weight_decay=1.0):
+                 device="cuda", reference="compressed", weight_decay=1.0, workspace=None):
+        """workspace: optional uint8 device tensor of at least workspace_size(...)
+        bytes that holds the driver's device state (the driver then allocates
+        nothing; the tensor must outlive it).  Without it the library
+        allocates the state itself."""
         lib = load()
         self.params = SequentialParams(R, C, M, K_max, tuple(window), alpha, precision, method, reference,
                                        weight_decay)
@@ -613,8 +620,24 @@ class Sequential:
                        _PREC[precision], _METHOD[method], _REFERENCE[reference], float(weight_decay))
         h = _P()
         with torch.cuda.device(self.device):
-            _check(lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)), "Sequential")
+            if workspace is None:
+                _check(lib.pl_seq_create(ctypes.byref(p), ctypes.byref(h)), "Sequential")
+            else:
+                _need(workspace, torch.uint8, 1, "Sequential(workspace)")
+                _check(lib.pl_seq_create_in(ctypes.byref(p), _ptr(workspace), workspace.numel(), ctypes.byref(h)),
+                       "Sequential")
+        self._ws = workspace
         self._h = h
+
+    @staticmethod
+    def workspace_size(R, C, M, K_max, window, alpha=1e-3, precision="fp32", method="emi",
+                       reference="compressed", weight_decay=1.0) -> int:
+        """Bytes of device state of a driver with these parameters."""
+        p = _SeqParams(int(R), int(C), int(M), int(K_max), _win(window), float(alpha),
+                       _PREC[precision], _METHOD[method], _REFERENCE[reference], float(weight_decay))
+        n = ctypes.c_size_t()
+        _check(load().pl_seq_workspace_size(ctypes.byref(p), ctypes.byref(n)), "Sequential.workspace_size")
+        return n.value
 
     def close(self):
         if getattr(self, "_h", None):

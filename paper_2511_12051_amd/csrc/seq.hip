@@ -26,6 +26,7 @@ struct pl_seq {
     float2* coh = nullptr;      // [opix][N][N], N = M + K_max
     float2* phasors = nullptr;  // [N][opix]
     uint8_t* flags = nullptr;   // [opix]
+    void* owned = nullptr;      // the device block, when the driver allocated it
 };
 
 namespace {
@@ -42,22 +43,56 @@ struct CkptHeader {
     double weight_decay;
 };
 
-template <class T>
-pl_status alloc(T** p, size_t n, const char* what) {
-    return hip_ok(hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T)), what);
+// Device state in one block: each array starts on a 256-byte boundary.  With
+// base == nullptr only the size is computed.
+size_t carve(pl_seq* s, unsigned char* base) {
+    const pl_seq_params& p = s->p;
+    const int N = p.M + p.K_max;
+    size_t off = 0;
+    auto take = [&]<class T>(T** ptr, size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        *ptr = base && n ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += n * sizeof(T);
+    };
+    take(&s->kappa, (size_t)p.K_max * s->plane);
+    take(&s->means, (size_t)(p.K_max + 1) * s->plane);
+    take(&s->vars, (size_t)(p.K_max + 1) * s->plane);
+    take(&s->mean_m, (size_t)s->plane);
+    take(&s->var_m, (size_t)s->plane);
+    take(&s->mask, (size_t)s->opix * s->g.nw);
+    take(&s->cnt, (size_t)s->opix);
+    take(&s->coh, (size_t)s->opix * N * N);
+    take(&s->phasors, (size_t)s->opix * N);
+    take(&s->flags, (size_t)s->opix);
+    return (off + 255) & ~(size_t)255;
 }
 
 void release(pl_seq* s) {
-    hipFree(s->kappa);
-    hipFree(s->means);
-    hipFree(s->vars);
-    hipFree(s->mean_m);
-    hipFree(s->var_m);
-    hipFree(s->mask);
-    hipFree(s->cnt);
-    hipFree(s->coh);
-    hipFree(s->phasors);
-    hipFree(s->flags);
+    if (s->owned) (void)hipFree(s->owned);
+    s->owned = nullptr;
+}
+
+// checks the parameters and fills the host part of the driver
+pl_status setup(const pl_seq_params* params, pl_seq* s, const char* fn) {
+    const pl_seq_params& p = *params;
+    Geometry g;
+    if (!make_geometry(p.R, p.C, p.w, &g) || g.oR < 1 || g.oC < 1)
+        return fail(PL_ERR_SHAPE, "%s: bad image size or window", fn);
+    if (p.M < 1 || p.K_max < 0 || p.M + p.K_max > kMaxN)
+        return fail(PL_ERR_UNSUPPORTED, "%s: need 1 <= M and M + K_max <= %d", fn, kMaxN);
+    if (!(p.alpha > 0 && p.alpha < 1)) return fail(PL_ERR_INVALID_ARG, "%s: alpha outside (0,1)", fn);
+    if (p.precision != PL_PREC_FP32 && p.precision != PL_PREC_SPLIT_BF16)
+        return fail(PL_ERR_INVALID_ARG, "%s: unknown precision", fn);
+    if (p.method != PL_LINK_EMI && p.method != PL_LINK_EVD) return fail(PL_ERR_INVALID_ARG, "%s: unknown method", fn);
+    if (p.reference != PL_SEQ_REF_COMPRESSED && p.reference != PL_SEQ_REF_LAST)
+        return fail(PL_ERR_INVALID_ARG, "%s: unknown reference mode", fn);
+    if (!(p.weight_decay > 0 && p.weight_decay <= 1))
+        return fail(PL_ERR_INVALID_ARG, "%s: weight_decay outside (0, 1]", fn);
+    s->p = p;
+    s->g = g;
+    s->plane = p.R * p.C;
+    s->opix = g.oR * g.oC;
+    return PL_OK;
 }
 
 size_t state_bytes(const pl_seq* s) {
@@ -69,46 +104,46 @@ size_t state_bytes(const pl_seq* s) {
 
 extern "C" {
 
+pl_status pl_seq_workspace_size(const pl_seq_params* params, size_t* bytes) {
+    if (!params || !bytes) return fail(PL_ERR_INVALID_ARG, "pl_seq_workspace_size: NULL pointer");
+    pl_seq s;
+    const pl_status st = setup(params, &s, "pl_seq_workspace_size");
+    if (st != PL_OK) return st;
+    *bytes = carve(&s, nullptr);
+    return PL_OK;
+}
+
+pl_status pl_seq_create_in(const pl_seq_params* params, void* dev_workspace, size_t bytes, pl_seq** out) {
+    if (!params || !out || !dev_workspace) return fail(PL_ERR_INVALID_ARG, "pl_seq_create_in: NULL pointer");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) & 255)
+        return fail(PL_ERR_INVALID_ARG, "pl_seq_create_in: workspace not 256-byte aligned");
+    pl_seq* s = new (std::nothrow) pl_seq();
+    if (!s) return fail(PL_ERR_WORKSPACE, "pl_seq_create_in: out of host memory");
+    pl_status st = setup(params, s, "pl_seq_create_in");
+    if (st == PL_OK && bytes < carve(s, nullptr))
+        st = fail(PL_ERR_WORKSPACE, "pl_seq_create_in: workspace of %zu bytes, the driver needs %zu", bytes,
+                  carve(s, nullptr));
+    if (st != PL_OK) {
+        delete s;
+        return st;
+    }
+    carve(s, static_cast<unsigned char*>(dev_workspace));
+    *out = s;
+    return PL_OK;
+}
+
 pl_status pl_seq_create(const pl_seq_params* params, pl_seq** out) {
     if (!params || !out) return fail(PL_ERR_INVALID_ARG, "pl_seq_create: NULL pointer");
-    const pl_seq_params& p = *params;
-    Geometry g;
-    if (!make_geometry(p.R, p.C, p.w, &g) || g.oR < 1 || g.oC < 1)
-        return fail(PL_ERR_SHAPE, "pl_seq_create: bad image size or window");
-    if (p.M < 1 || p.K_max < 0 || p.M + p.K_max > kMaxN)
-        return fail(PL_ERR_UNSUPPORTED, "pl_seq_create: need 1 <= M and M + K_max <= %d", kMaxN);
-    if (!(p.alpha > 0 && p.alpha < 1)) return fail(PL_ERR_INVALID_ARG, "pl_seq_create: alpha outside (0,1)");
-    if (p.precision != PL_PREC_FP32 && p.precision != PL_PREC_SPLIT_BF16)
-        return fail(PL_ERR_INVALID_ARG, "pl_seq_create: unknown precision");
-    if (p.method != PL_LINK_EMI && p.method != PL_LINK_EVD)
-        return fail(PL_ERR_INVALID_ARG, "pl_seq_create: unknown method");
-    if (p.reference != PL_SEQ_REF_COMPRESSED && p.reference != PL_SEQ_REF_LAST)
-        return fail(PL_ERR_INVALID_ARG, "pl_seq_create: unknown reference mode");
-    if (!(p.weight_decay > 0 && p.weight_decay <= 1))
-        return fail(PL_ERR_INVALID_ARG, "pl_seq_create: weight_decay outside (0, 1]");
     pl_seq* s = new (std::nothrow) pl_seq();
     if (!s) return fail(PL_ERR_WORKSPACE, "pl_seq_create: out of host memory");
-    s->p = p;
-    s->g = g;
-    s->plane = p.R * p.C;
-    s->opix = g.oR * g.oC;
-    const int N = p.M + p.K_max;
-    pl_status st = PL_OK;
-    if (p.K_max > 0 && st == PL_OK) st = alloc(&s->kappa, (size_t)p.K_max * s->plane, "pl_seq_create: kappa ring");
-    if (st == PL_OK) st = alloc(&s->means, (size_t)(p.K_max + 1) * s->plane, "pl_seq_create: statistics");
-    if (st == PL_OK) st = alloc(&s->vars, (size_t)(p.K_max + 1) * s->plane, "pl_seq_create: statistics");
-    if (st == PL_OK) st = alloc(&s->mean_m, (size_t)s->plane, "pl_seq_create: merged statistics");
-    if (st == PL_OK) st = alloc(&s->var_m, (size_t)s->plane, "pl_seq_create: merged statistics");
-    if (st == PL_OK) st = alloc(&s->mask, (size_t)s->opix * g.nw, "pl_seq_create: masks");
-    if (st == PL_OK) st = alloc(&s->cnt, (size_t)s->opix, "pl_seq_create: counts");
-    if (st == PL_OK) st = alloc(&s->coh, (size_t)s->opix * N * N, "pl_seq_create: coherence");
-    if (st == PL_OK) st = alloc(&s->phasors, (size_t)s->opix * N, "pl_seq_create: phasors");
-    if (st == PL_OK) st = alloc(&s->flags, (size_t)s->opix, "pl_seq_create: flags");
+    pl_status st = setup(params, s, "pl_seq_create");
+    if (st == PL_OK) st = hip_ok(hipMalloc(&s->owned, carve(s, nullptr)), "pl_seq_create: device state");
     if (st != PL_OK) {
         release(s);
         delete s;
         return st;
     }
+    carve(s, static_cast<unsigned char*>(s->owned));
     *out = s;
     return PL_OK;
 }

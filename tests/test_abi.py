@@ -179,3 +179,34 @@ def test_batch_argument_checks(lib):
     assert lib.pl_batch_plan((plink._BatchItem * 1)(it), 1, w, 1e-3, 0, 0, 0, None, ctypes.byref(h)) == 1
     assert lib.pl_batch_destroy(None) == 0
     assert lib.pl_batch_run(None, None) == 1
+
+
+def test_sequential_workspace_size_and_checks(lib):
+    """The driver's device state in one block: its size is a host query, it
+    grows with K_max exactly by the compressed-SLC ring and one more set of
+    statistics, and creating a driver in a too-small or misaligned buffer is
+    rejected before any device work."""
+    w = (11, 5, 6, 3)
+    R, C, M = 96, 198, 15
+    n0 = plink.Sequential.workspace_size(R, C, M, 0, w)
+    n2 = plink.Sequential.workspace_size(R, C, M, 2, w)
+    oR, oC = plink.output_grid(R, C, w)
+    px, P = R * C, oR * oC
+
+    def up(v):
+        return (v + 255) // 256 * 256
+
+    # K_max = 2 adds the ring of two compressed SLCs, two more statistics
+    # planes pairs, and the wider coherence and phasors of N = M + 2
+    grow = up(2 * px * 8) + 2 * up(px * 8 * 3) - 2 * up(px * 8) \
+        + up(P * (M + 2) ** 2 * 8) - up(P * M * M * 8) + up(P * (M + 2) * 8) - up(P * M * 8)
+    assert n2 - n0 == grow
+    p = plink._SeqParams(R, C, M, 2, plink._win(w), 1e-3, 0, 0, 0, 1.0)
+    h = plink._P()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.pl_seq_create_in(ctypes.byref(p), fake, n2 - 1, ctypes.byref(h)) == 5   # PL_ERR_WORKSPACE
+    assert lib.pl_seq_create_in(ctypes.byref(p), ctypes.c_void_p(0x1010), n2, ctypes.byref(h)) == 1  # misaligned
+    assert lib.pl_seq_create_in(ctypes.byref(p), None, n2, ctypes.byref(h)) == 1
+    bad = plink._SeqParams(R, C, 0, 2, plink._win(w), 1e-3, 0, 0, 0, 1.0)
+    n = ctypes.c_size_t()
+    assert lib.pl_seq_workspace_size(ctypes.byref(bad), ctypes.byref(n)) == 3

@@ -127,6 +127,25 @@ def test_append_only_and_resume_bit_identical(gpu_lib):
             assert np.array_equal(x, y)
 
 
+def test_driver_in_caller_workspace_matches(gpu_lib):
+    """A driver whose device state lives in the caller's buffer gives the same
+    bits as one that allocates its own; a smaller buffer is refused."""
+    wl, z = _sequence(seed=34, ministacks=3)
+    K, M = 2, wl.n_new
+    _, ref = _run_gpu(gpu_lib, wl, z, K, ministacks=3)
+    n = gpu_lib.Sequential.workspace_size(wl.R, wl.C, M, K, wl.window, wl.alpha)
+    ws = torch.full((n,), 0xA5, dtype=torch.uint8, device="cuda")  # stale contents must not matter
+    seq = gpu_lib.Sequential(wl.R, wl.C, M, K, wl.window, wl.alpha, workspace=ws)
+    zc = z.cuda()
+    for k in range(3):
+        ph, kap, fl = seq.push(zc[k * M:(k + 1) * M].contiguous(), want_flags=True)
+        for x, y in zip((ph.cpu().numpy(), kap.cpu().numpy(), fl.cpu().numpy()), ref[k]):
+            assert np.array_equal(x, y)
+    seq.close()
+    with pytest.raises(gpu_lib.PlinkError):
+        gpu_lib.Sequential(wl.R, wl.C, M, K, wl.window, wl.alpha, workspace=ws[: n - 256])
+
+
 def test_checkpoint_rejects_other_geometry(gpu_lib):
     wl, z = _sequence(seed=33, ministacks=1)
     seq, _ = _run_gpu(gpu_lib, wl, z, 2, ministacks=1)
