@@ -16,7 +16,9 @@
 // dropped:  Re A = Whh + Whl + Whl^T  with Whl = sum s (r_h r_l^T + i_h i_l^T),
 // S = V1 + V2^T with V1 = sum s r_h (i_h + i_l)^T, V2 = sum s i_h r_l^T, so
 // Im A = U - U^T with U = V2 - V1;  seven v_mfma_f32_{16x16x32,32x32x16}_bf16
-// per k-step.
+// per k-step.  32-row tiles keep all six products of each of Re A and Im A
+// (twelve MFMAs per k-step) instead of forming the transposed terms through
+// LDS, which frees the transpose scratch for a wider strip of the ring.
 //
 // Data movement: a workgroup owns a strip of TXo output columns and walks
 // down a band of output rows.  The window rows it needs live in an LDS ring
@@ -126,7 +128,7 @@ __device__ __forceinline__ Items make_items(const CohArgs& a, int nthreads) {
 // stay in registers); any other unit is staged directly at commit time.
 constexpr int kPfItems = 2;
 template <int NT>
-constexpr int kPfRows = NT == 16 ? 3 : 2;
+constexpr int kPfRows = 3;
 
 template <int NT>
 struct RowLoad {
@@ -299,11 +301,12 @@ __device__ __forceinline__ void transpose_read(float* S, const typename Acc<NT>:
 }
 
 // Normalise and store one pixel's matrix from Re/Im in accumulator layout.
-template <int NT>
+template <int NT, bool SPLIT>
 __device__ void store_pixel(const CohArgs& a, float* S, const typename Acc<NT>::T& re,
                             const typename Acc<NT>::T& im, int64_t pix, int lane) {
     constexpr int LD = NT + 1;
-    float* diag = S + NT * LD;
+    // the transpose-free split path keeps only the diagonal in the wave's scratch
+    float* diag = S + (SPLIT && NT == 32 ? 0 : NT * LD);
     const int j = lane & (NT - 1);
     const int N = a.N;
 #pragma unroll
@@ -345,7 +348,56 @@ __device__ void pixel_gram(const CohArgs& a, const void* lds, const uint32_t* ta
     const int dd = live ? d : a.N - 1;
     const uint32_t live_mask = live ? 0xffffffffu : 0u;
     AT whh = {}, v1 = {};
-    if constexpr (SPLIT) {
+    if constexpr (SPLIT && NT == 32) {
+        // 32-row tiles: both triangles of Re A and Im A straight from the
+        // MFMAs, so no transpose (and no transpose scratch in LDS):
+        //   Re A = sum s (rh rh + rh rl + rl rh + ih ih + ih il + il ih)
+        //   Im A = sum s (ih rh + ih rl + il rh) - sum s (rh ih + rh il + rl ih)
+        // with the SHP bit on the A operand of every product (row index m).
+        AT re1 = {}, imn = {};
+        constexpr int PPK = 8;  // pairs per k-step
+        const u32x4* P = reinterpret_cast<const u32x4*>(lds) + dd * a.plane;
+        const u32x4* E = reinterpret_cast<const u32x4*>(table) + 2 * g;  // 4 entries per group
+        u32x4 e01 = E[0], e23 = E[1];
+        for (int ks = 0; ks < npad; ks += PPK) {
+            const u32x4 q0 = P[e01[0]], q1 = P[e01[2]], q2 = P[e23[0]], q3 = P[e23[2]];
+            u32x4 n01 = e01, n23 = e23;
+            if (ks + PPK < npad) {
+                n01 = E[(ks + PPK) / 2];
+                n23 = E[(ks + PPK) / 2 + 1];
+            }
+            const uint32_t m0 = e01[1] & live_mask, m1 = e01[3] & live_mask;
+            const uint32_t m2 = e23[1] & live_mask, m3 = e23[3] & live_mask;
+            const u32x4 rh = {q0[0], q1[0], q2[0], q3[0]}, rl = {q0[1], q1[1], q2[1], q3[1]};
+            const u32x4 ih = {q0[2], q1[2], q2[2], q3[2]}, il = {q0[3], q1[3], q2[3], q3[3]};
+            const u32x4 rhm = {q0[0] & m0, q1[0] & m1, q2[0] & m2, q3[0] & m3};
+            const u32x4 rlm = {q0[1] & m0, q1[1] & m1, q2[1] & m2, q3[1] & m3};
+            const u32x4 ihm = {q0[2] & m0, q1[2] & m1, q2[2] & m2, q3[2] & m3};
+            const u32x4 ilm = {q0[3] & m0, q1[3] & m1, q2[3] & m2, q3[3] & m3};
+            const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh), Rl = __builtin_bit_cast(bf16x8, rl);
+            const bf16x8 Ih = __builtin_bit_cast(bf16x8, ih), Il = __builtin_bit_cast(bf16x8, il);
+            const bf16x8 Rhm = __builtin_bit_cast(bf16x8, rhm), Rlm = __builtin_bit_cast(bf16x8, rlm);
+            const bf16x8 Ihm = __builtin_bit_cast(bf16x8, ihm), Ilm = __builtin_bit_cast(bf16x8, ilm);
+            // four accumulation chains, interleaved
+            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Rh, whh, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Rh, v1, 0, 0, 0);
+            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Rl, re1, 0, 0, 0);
+            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Ih, imn, 0, 0, 0);
+            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rlm, Rh, whh, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Rl, v1, 0, 0, 0);
+            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Ih, re1, 0, 0, 0);
+            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Il, imn, 0, 0, 0);
+            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Il, whh, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ilm, Rh, v1, 0, 0, 0);
+            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ilm, Ih, re1, 0, 0, 0);
+            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rlm, Ih, imn, 0, 0, 0);
+            e01 = n01;
+            e23 = n23;
+        }
+        (void)S;
+        re = whh + re1;
+        im = v1 - imn;
+    } else if constexpr (SPLIT) {
         AT whl = {}, v2 = {};
         constexpr int PPK = NT == 16 ? 16 : 8;  // pairs per k-step
         const u32x4* P = reinterpret_cast<const u32x4*>(lds) + dd * a.plane;
@@ -472,7 +524,7 @@ __device__ void coherence_body(const CohArgs& a, const float2* const* planes, in
             wave_sync();
             typename Acc<NT>::T re, im;
             pixel_gram<NT, SPLIT>(a, lds_words, wave_area, npad, lane, re, im, S);
-            store_pixel<NT>(a, S, re, im, (oy - a.oy_lo) * g.oC + ox, lane);
+            store_pixel<NT, SPLIT>(a, S, re, im, (oy - a.oy_lo) * g.oC + ox, lane);
         }
         __syncthreads();  // every wave is done with the rows about to be replaced
         if (more) {
@@ -521,7 +573,8 @@ size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req
     const Geometry& g = a.g;
     const size_t lds_cap = max_lds_bytes();
     const int PPK = split ? (nt == 16 ? 16 : 8) : (nt == 16 ? 2 : 1);
-    const int scratch_words = nt * (nt + 1) + nt;
+    // transpose scratch and diagonal; the split 32-row path transposes nothing
+    const int scratch_words = (split && nt == 32) ? nt : nt * (nt + 1) + nt;
     const int table_words = ((2 * (a.n_pairs + PPK) + 3) / 4) * 4;
     a.wave_words = ((scratch_words > table_words ? scratch_words : table_words) + 3) / 4 * 4;
     int chosen = 0;
@@ -623,7 +676,7 @@ pl_status launch_coherence_args(CohArgs& a, int prec, hipStream_t s) {
 const void* coherence_batch_fn(int nt, bool split) { return coherence_fn(nt, split, true); }
 
 int coherence_threads(int nt) { return 64 * waves_of(nt); }
-int coherence_strip(int nt) { return nt == 16 ? 12 : 16; }  // one output column per wavefront and row
+int coherence_strip(int nt) { return nt == 16 ? 12 : 8; }  // one output column per wavefront and row
 
 // the caller has raised the kernel's dynamic LDS limit (allow_dynamic_lds)
 pl_status launch_coherence_batch(const BatchRange<CohArgs>& r, int nt, bool split, size_t lds, int64_t grid,

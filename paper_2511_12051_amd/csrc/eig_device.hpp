@@ -1,7 +1,8 @@
 // Device building blocks of the per-pixel eigen-solve shared by the phase
 // linking kernel and its adjoint: group reductions, FP64 and complex FP32
-// Gauss-Jordan inversion, and shifted inverse iteration for the smallest
-// eigenpair of a Hermitian matrix.
+// Gauss-Jordan inversion, the matrix-core sweep that inverts one pixel's
+// shifted matrix for two-row groups, and shifted inverse iteration for the
+// smallest eigenpair of a Hermitian matrix.
 //
 // A group of NP lanes (inside one wavefront) owns one pixel, NJ >= N
 // columns per row.  Two forms:
@@ -15,6 +16,7 @@
 //    within a group need no barrier.
 #pragma once
 #include <cmath>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -766,6 +768,7 @@ struct BTriLds {
     static constexpr int cj(int j) { return j * (2 * NJ - j - 1) / 2; }
     float2* w;  // this wavefront's buffer
     int g, l, N;
+    float2* xs;  // this wavefront's 16 x 33 scratch for matrix-core factorisations
 
     __device__ __forceinline__ int up_base(int ll, int r) const {
         const int i = ll + 16 * r;
@@ -842,6 +845,200 @@ struct BTriLds {
     }
 };
 
+// ---- (B - mu I)^{-1} of one pixel on the matrix cores (two rows per lane,
+// N <= 32).  The whole wavefront works on one 16-lane group's matrix at a
+// time, held as two 32 x 32 FP32 accumulators (real and imaginary parts) in
+// the layout of v_mfma_f32_32x32x2f32: lane l holds column l % 32 of rows
+// acc_row(v, l / 32), v = 0..15.  Rows and columns at or beyond N are zero.
+//
+// Sweep operator on the Hermitian A = B - mu I: for each pivot k < N, with
+// p = a_kk and r = row k,
+//   a_ij <- a_ij - a_ik a_kj / p,  a_kj <- a_kj / p,  a_ik <- a_ik / p,
+//   a_kk <- -1 / p,
+// which keeps A Hermitian (column k is conj(row k)) and, after all pivots,
+// leaves -A^{-1}.  One step is one complex rank-1 update of the whole
+// matrix, two real rank-2 MFMAs: with f_i = conj(r_i) / p,
+//   Re A -= [-Re f | Im f] x [Re r ; Im r],  Im A -= [-Re f | -Im f] x [Im r ; Re r]
+// (A operand: lane l gives row l % 32, column l / 32; B operand: lane l gives
+// row l / 32, column l % 32).  Row and column k come out of the same update
+// when f_k is replaced by 1 - 1/p and r_k by p - 1, and the diagonal entry by
+// first subtracting 2 from a_kk:  (p - 2) - (1 - 1/p)(p - 1) = -1/p.
+// All pivots positive and finite proves mu < lambda_min(B) (Sylvester's
+// inertia), as with the Gauss-Jordan form.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ constexpr int acc_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
+
+// Operands of sweep step K for one accumulator pair (VALU part).  Row K
+// lives in register KV of the lanes of half KH; one v_permlane32_swap of
+// the real and imaginary registers in place leaves {Re r, Im r} in the
+// register of half KH (lane c: Re r_c, lane c + 32: Im r_c), which is
+// exactly the B operand of the real update, and {row K + 4 - 8 KH} in the
+// other; a second swap restores both.  The B operand of the imaginary
+// update has the halves exchanged.
+template <int K>
+__device__ __forceinline__ void sweep_operands(f32x16& ar, f32x16& ai, int lane, float& are, float& bre,
+                                               float& aim, float& bim, bool& pd) {
+    constexpr int KV = 4 * (K >> 3) + (K & 3), KH = (K >> 2) & 1;
+    const int c = lane & 31, h = lane >> 5;
+    float x = ar[KV], y = ai[KV];
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+    bre = KH ? y : x;  // lane c: Re r_c, lane c + 32: Im r_c
+    {
+        float u = x, w = y;  // restore the accumulators
+        asm volatile("v_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(u), "+v"(w));
+        ar[KV] = u;
+        ai[KV] = w;
+    }
+    float lo = bre, hi = bre;
+    asm volatile("v_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(lo), "+v"(hi));
+    bim = h ? lo : hi;  // lane c: Im r_c, lane c + 32: Re r_c
+    const float p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bre), K));
+    pd = pd && (p > 0.f) && (p <= 3.4e38f);
+    const float rp = __builtin_amdgcn_rcpf(p);
+    are = -bre * rp;          // -Re f_c (lane c), Im f_c (lane c + 32); f_c = conj(r_c) / p
+    aim = h ? -are : are;     // -Re f_c, -Im f_c
+    if (c == K) {
+        const float phi = 1.f - rp, rho = p - 1.f;
+        are = h ? 0.f : -phi;
+        aim = are;
+        bre = h ? 0.f : rho;
+        bim = h ? rho : 0.f;
+    }
+}
+
+// Steps K onwards for one (TWO = false) or two independent matrices; each
+// matrix's MFMAs are issued before the other's operands are formed, so that
+// they overlap each other's latency (scheduling barriers keep that order).
+template <int NJ, int K, bool TWO>
+__device__ __forceinline__ void sweep_steps(f32x16& ar0, f32x16& ai0, f32x16& ar1, f32x16& ai1, int N, int lane,
+                                            bool& pd0, bool& pd1) {
+    if constexpr (K < NJ) {
+        constexpr int KV = 4 * (K >> 3) + (K & 3), KH = (K >> 2) & 1;
+        if (K < kMinN<NJ> || K < N) {
+            const float two = lane == K + 32 * KH ? 2.f : 0.f;
+            float a0, b0, c0, d0;
+            sweep_operands<K>(ar0, ai0, lane, a0, b0, c0, d0, pd0);
+            ar0[KV] -= two;
+            ar0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, ar0, 0, 0, 0);
+            ai0 = __builtin_amdgcn_mfma_f32_32x32x2f32(c0, d0, ai0, 0, 0, 0);
+            if constexpr (TWO) {
+                __builtin_amdgcn_sched_barrier(0);
+                float a1, b1, c1, d1;
+                sweep_operands<K>(ar1, ai1, lane, a1, b1, c1, d1, pd1);
+                ar1[KV] -= two;
+                ar1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, ar1, 0, 0, 0);
+                ai1 = __builtin_amdgcn_mfma_f32_32x32x2f32(c1, d1, ai1, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        sweep_steps<NJ, K + 1, TWO>(ar0, ai0, ar1, ai1, N, lane, pd0, pd1);
+    }
+}
+
+// A = B - mu I of group g in accumulator layout: entry (i, c) of the
+// Hermitian matrix of the upper triangle; zero outside N x N.
+template <int NJ>
+__device__ __forceinline__ void acc_load(const BTriLds<NJ>& tri, int g, float mu, int N, int lane, f32x16& ar,
+                                         f32x16& ai) {
+    const int c = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = acc_row(v, h);
+        const int lo = i < c ? i : c, hi = i < c ? c : i;
+        const bool in = i < N && c < N;
+        const int e = in ? (lo * (2 * NJ - lo - 1)) / 2 + hi : 0;
+        const float2 b = tri.w[e * BTriLds<NJ>::GPW + g];
+        ar[v] = in ? b.x - (i == c ? mu : 0.f) : 0.f;
+        ai[v] = in ? (i > c ? -b.y : b.y) : 0.f;
+    }
+}
+
+// The sweep result S = -A^{-1} into the rows l, l + 16 of group g's lanes.
+// S is Hermitian, so row t is the conjugate of column t, which lanes t and
+// t + 32 hold: they write it conjugated into the wave's 16 x 33 scratch as
+// a row (16 rows per pass), and lane t % 16 of group g reads it back.
+template <int NJ>
+__device__ __forceinline__ void acc_to_rows(const f32x16& ar, const f32x16& ai, int g, int lane, float2* xs,
+                                            float2 (&m)[2][NJ]) {
+    const int c = lane & 31, h = lane >> 5;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        wave_sync();  // the previous reads of the scratch are done
+        if ((c >> 4) == s) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) xs[(c & 15) * 33 + acc_row(v, h)] = make_float2(ar[v], -ai[v]);
+        }
+        wave_sync();
+        if ((lane >> 4) == g) {
+            const float2* row = xs + (lane & 15) * 33;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) m[s][j] = row[j];
+        }
+    }
+}
+
+// -(B - mu I)^{-1} for every 16-lane group g of the wavefront with need
+// (mu from the group's lanes), written into the rows l, l + 16 (m[0], m[1])
+// of that group's lanes.  (Inverse iteration with the gauge fix gives the
+// same iterates for -M as for M: the sign is a unit factor that the gauge
+// rotation removes exactly.)  B is read from the packed triangle view `tri`;
+// xs is the wavefront's 16 x 33 scratch.
+//  - Three or four groups waiting: every group is factored, two at a time so
+//    that the two matrices' MFMAs overlap each other's latency; groups
+//    without a request redo their accepted shift, which reproduces their m
+//    exactly (m's old contents are dead on this path).
+//  - Fewer: one group at a time, the other groups' m left as it was.
+// Returns, for this lane's group, whether every pivot was positive and
+// finite (meaningful where need).
+template <int NJ>
+__device__ __forceinline__ bool factor_mfma(float2 (&m)[2][NJ], const BTriLds<NJ>& tri, float2* xs, float mu,
+                                            bool need, int N) {
+    static_assert(NJ <= 32, "32 x 32 accumulators");
+    const uint64_t want = __ballot(need);
+    int pending = (int)((want & 1ull) | ((want >> 15) & 2ull) | ((want >> 30) & 4ull) | ((want >> 45) & 8ull));
+    bool ok = true;
+    if (__builtin_popcount(pending) >= 3) {
+        float2 t[2][NJ];  // every lane's rows are written by exactly one group's pass
+#pragma unroll
+        for (int q = 0; q < 4; q += 2) {
+            const int lane = opaque_int(lane_id());
+            const int grp = lane >> 4;
+            const float mu0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mu), 16 * q));
+            const float mu1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mu), 16 * q + 16));
+            f32x16 ar0, ai0, ar1, ai1;
+            acc_load<NJ>(tri, q, mu0, N, lane, ar0, ai0);
+            acc_load<NJ>(tri, q + 1, mu1, N, lane, ar1, ai1);
+            bool pd0 = true, pd1 = true;
+            sweep_steps<NJ, 0, true>(ar0, ai0, ar1, ai1, N, lane, pd0, pd1);
+            acc_to_rows<NJ>(ar0, ai0, q, lane, xs, t);
+            acc_to_rows<NJ>(ar1, ai1, q + 1, lane, xs, t);
+            if (grp == q) ok = pd0;
+            if (grp == q + 1) ok = pd1;
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) m[r][j] = t[r][j];
+        return ok;
+    }
+    while (pending) {  // uniform
+        const int g = __builtin_ctz(pending);
+        pending &= pending - 1;
+        // an opaque lane index: the per-step lane predicates and offsets are
+        // formed inside the loop instead of being hoisted and kept live
+        const int lane = opaque_int(lane_id());
+        const float mug = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mu), 16 * g));
+        f32x16 ar, ai, unused0, unused1;
+        acc_load<NJ>(tri, g, mug, N, lane, ar, ai);
+        bool pd = true, pd1 = true;
+        sweep_steps<NJ, 0, false>(ar, ai, unused0, unused1, N, lane, pd, pd1);
+        acc_to_rows<NJ>(ar, ai, g, lane, xs, m);
+        if ((lane >> 4) == g) ok = pd;
+    }
+    return ok;
+}
+
 // Eigenvector of the smallest eigenvalue of the Hermitian B (rows held as
 // the view bv describes) by shifted inverse iteration starting from x (unit
 // norm; R components per lane).  On return m holds (B - mu I)^{-1} for the
@@ -877,9 +1074,16 @@ __device__ __forceinline__ void eig_min_r(float2 (&m)[R][NJ], const BV& bv, floa
             // 16-lane groups: every group of the wavefront factors; those
             // without a pending request redo their accepted shift, which
             // reproduces their inverse exactly
-            if constexpr (NP == 16) bv.load(m, true);
-            else bv.load(m, need);
-            const bool ok = factor_c<NP, R, NJ>(m, need ? mu_req : mu, N, i, need, rbc0, rbc1);
+            bool ok;
+            if constexpr (NP == 16 && R == 2 && std::is_same_v<BV, BTriLds<NJ>>) {
+                // two rows per lane: per pixel on the matrix cores, only the
+                // groups that wait for a factorisation
+                ok = factor_mfma<NJ>(m, bv, bv.xs, need ? mu_req : mu, need, N);
+            } else {
+                if constexpr (NP == 16) bv.load(m, true);
+                else bv.load(m, need);
+                ok = factor_c<NP, R, NJ>(m, need ? mu_req : mu, N, i, need, rbc0, rbc1);
+            }
             if (need) {
                 if (ok) {
                     if (stage == 4) d2prev = 0.f;  // the contraction rate changes

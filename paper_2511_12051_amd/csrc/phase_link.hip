@@ -12,8 +12,11 @@
 //     failed and the pixel takes the EVD branch.
 //  2. B = G^{-1} o C (EMI) or B = -C (EVD); both need the eigenvector of the
 //     smallest eigenvalue of the Hermitian B.
-//  3. Shifted inverse iteration with an explicit (B - mu I)^{-1}, formed by
-//     complex Gauss-Jordan in FP32.  All pivots positive proves
+//  3. Shifted inverse iteration with an explicit (B - mu I)^{-1} in FP32,
+//     formed by complex Gauss-Jordan on the vector ALUs for N <= 16 and, for
+//     N > 16, by a Hermitian sweep on the matrix cores, one pixel's matrix
+//     per 32 x 32 accumulator pair (each step a complex rank-1 update, two
+//     v_mfma_f32_32x32x2f32).  All pivots positive proves
 //     mu < lambda_min (Sylvester's inertia), so the iteration converges to the
 //     wanted eigenvector.  EMI starts from mu = 0.99 (Sec. 3.2) and backs off
 //     if the inertia check fails; EVD starts from minus the largest absolute
@@ -54,7 +57,10 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
     // (R = 1), or the packed upper triangle of each group's matrix (R = 2),
     // which is also where B is formed from C.
     using Tri = BTriLds<NJ>;
-    constexpr int LDS_BYTES = R == 1 ? NJ * kBlock * 8 : (kBlock / 64) * Tri::WAVE_ENTRIES * 8;
+    // two-row groups: the triangle and a 16 x 33 scratch per wavefront for the
+    // matrix-core factorisations
+    constexpr int XS = 16 * 33;
+    constexpr int LDS_BYTES = R == 1 ? NJ * kBlock * 8 : (kBlock / 64) * (Tri::WAVE_ENTRIES + XS) * 8;
     __shared__ __attribute__((aligned(16))) float2 lds[LDS_BYTES / 8];
     // opaque copies of the lane index and N: in a persistent loop the
     // compiler would otherwise precompute every per-step constant and
@@ -145,7 +151,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block) {
             x[r].y *= q;
         }
     }
-    const Tri tri{lds + wave * Tri::WAVE_ENTRIES, grp, l, N};
+    const Tri tri{lds + wave * Tri::WAVE_ENTRIES, grp, l, N, lds + (kBlock / 64) * Tri::WAVE_ENTRIES + wave * XS};
     if constexpr (R == 2) {
         // C's upper triangle goes to LDS now; B is formed there after step 1.
         // The fence orders these stores after the previous pixel's reads of
