@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--only-main", action="store_true",
                     help="skip the other-workload, batched-sequence and adjoint legs")
+    ap.add_argument("--only-sequence", action="store_true",
+                    help="only the batched-sequence leg (4 bursts x 8 mini-stacks)")
     ap.add_argument("--skip-fused", action="store_true", help="do not time the fused coherence + linking step")
     ap.add_argument("--cpu-workers", type=int, default=0,
                     help="oracle worker processes (default: the usable host cores, at most 16)")
@@ -449,9 +451,16 @@ def leg_sequence(torch, plink, synth, args, prec):
     t0 = time.perf_counter()
     batch = plink.Batch(items, wl.window, wl.alpha, precision=prec, autotune=True)
     plan_s = time.perf_counter() - t0
-    batch.run()  # captures the graph
+    batch.run()  # captures the graph (one persistent launch per run)
     ms = time_steps(torch, batch.run, 10, 3)["median"]
+    batch.check()
     desc = batch.describe()
+    # the same plan as one launch per stage and kernel variant
+    batch.set_single_launch(False)
+    batch.run()
+    ms_stages = time_steps(torch, batch.run, 10, 3)["median"]
+    launches_stages = int(batch.describe().strip().splitlines()[-1].split()[-1])
+    batch.set_single_launch(True)
 
     def driver():
         for z in seqs:
@@ -468,7 +477,9 @@ def leg_sequence(torch, plink, synth, args, prec):
             "precision": prec, "value": px / (ms * 1e-3), "unit": "pixels/s", "ms_per_run": ms,
             "output_pixels": px, "driver_ms": ms_driver, "speedup_vs_driver": ms_driver / ms,
             "plan_and_autotune_s": plan_s,
-            "launches_per_run": int(desc.strip().splitlines()[-1].split()[-1])}
+            "launches_per_run": int(desc.strip().splitlines()[-1].split()[-1]),
+            "stage_launches": {"ms_per_run": ms_stages, "launches_per_run": launches_stages,
+                               "value": px / (ms_stages * 1e-3)}}
 
 
 def leg_adjoint(torch, plink, synth, args):
@@ -520,6 +531,9 @@ def main():
     import paper_2511_12051_amd as plink
     import synth
     plink.load()
+    if args.only_sequence:
+        print(json.dumps(leg_sequence(torch, plink, synth, args, args.precision)), flush=True)
+        return
     wl = synth.WORKLOADS[args.workload]
     print(f"[bench] generating {wl.name} {wl.N}x{wl.R}x{wl.C} on cuda:0", file=sys.stderr, flush=True)
     stack = synth.make_stack(wl, seed=args.seed, device="cuda")

@@ -424,6 +424,22 @@ pl_status pl_batch_destroy(pl_batch* b);
 /* Text summary of the plan: launches, kernel variants, tiles, grid sizes and
  * (after a run) whether a graph is held.  Writes at most len bytes. */
 pl_status pl_batch_describe(const pl_batch* b, char* buf, size_t len);
+/* Chooses how pl_batch_run executes the plan (host call; synchronises the
+ * plan's stream and drops a captured graph).  on != 0: the whole run as ONE
+ * persistent launch (the default whenever the plan supports it): every
+ * (item, stage) pair is a segment of work units in one device-wide queue,
+ * in dependency order, and a workgroup starts a segment only after the
+ * segments it depends on are complete (the item's previous stage; for
+ * coherence also the compression of each item whose compressed SLC it reads,
+ * Sec. 2.2, Fig. 1).  on == 0: one persistent launch per stage and kernel
+ * variant, as above.  Both forms give bit-identical results.
+ * PL_ERR_UNSUPPORTED when the plan cannot run as one launch (pl_batch_describe
+ * gives the reason: a tile that does not fit one 512-thread workgroup). */
+pl_status pl_batch_set_single_launch(pl_batch* b, int32_t on);
+/* Synchronises `stream` and the plan's stream; PL_ERR_STATE if a
+ * single-launch run ever waited past its bound (about 0.25 s per wait;
+ * the run then completed without its ordering guarantee). */
+pl_status pl_batch_check(pl_batch* b, pl_stream stream);
 
 #ifdef __cplusplus
 }

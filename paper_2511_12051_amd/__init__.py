@@ -117,6 +117,8 @@ _SIGNATURES = {
     "pl_batch_run": (ctypes.c_int, [_P, _P]),
     "pl_batch_destroy": (ctypes.c_int, [_P]),
     "pl_batch_describe": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
+    "pl_batch_set_single_launch": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "pl_batch_check": (ctypes.c_int, [_P, ctypes.c_void_p]),
     "pl_seq_create": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(_P)]),
     "pl_seq_workspace_size": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(ctypes.c_size_t)]),
     "pl_seq_create_in": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.c_void_p, ctypes.c_size_t,
@@ -569,6 +571,17 @@ class Batch:
         buf = ctypes.create_string_buffer(8192)
         _check(load().pl_batch_describe(self._h, buf, len(buf)), "Batch describe")
         return buf.value.decode()
+
+    def set_single_launch(self, on: bool):
+        """True: each run is one persistent launch over every item and stage
+        (the default when the plan supports it); False: one launch per stage
+        and kernel variant."""
+        _check(load().pl_batch_set_single_launch(self._h, int(bool(on))), "Batch.set_single_launch")
+
+    def check(self):
+        """Synchronises and raises if a single-launch run waited past its bound."""
+        _check(load().pl_batch_check(self._h, _P(torch.cuda.current_stream(self._device).cuda_stream)),
+               "Batch.check")
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -80,8 +80,33 @@ struct Level {
 
 }  // namespace
 
+// per-item arguments of every stage, kept for the single-launch form
+struct ItemArgs {
+    bool has_stats = false, stats_vec = false, has_comp = false;
+    StatsArgs stats{};
+    int64_t stats_blocks = 0;
+    GlrtArgs glrt{};
+    int64_t glrt_blocks = 0;
+    size_t glrt_lds = 0;
+    CohArgs coh{};
+    LinkArgs link{};
+    int64_t link_blocks = 0;
+    CompressArgs comp{};
+    int64_t comp_blocks = 0;
+};
+
 struct pl_batch {
     std::vector<pl_batch_item> items;
+    std::vector<ItemArgs> iargs;
+    // single-launch form: the whole run as one persistent kernel
+    bool single = false, single_ok = false;
+    std::string single_why;
+    void* mega_mem = nullptr;
+    MegaPlan mega{};
+    int mega_nseg = 0;
+    size_t mega_lds = 0;
+    int64_t mega_grid = 0;
+    float mega_ms = -1.f, graph_ms = -1.f;
     std::vector<void*> allocations;
     std::vector<int> level_ids;  // distinct levels, increasing
     std::vector<Level> levels;
@@ -175,6 +200,7 @@ pl_status enqueue_level(pl_batch* b, Level& L, hipStream_t s) {
 }
 
 pl_status enqueue_all(pl_batch* b, hipStream_t s) {
+    if (b->single) return launch_mega(b->mega, b->split, b->mega_lds, b->mega_grid, s);
     for (auto& L : b->levels) {
         pl_status st = enqueue_level(b, L, s);
         if (st != PL_OK) return st;
@@ -272,6 +298,168 @@ pl_status autotune(pl_batch* b) {
     return hip_ok(hipStreamSynchronize(s), "pl_batch_plan: autotune");
 }
 
+// The single-launch plan: one segment per (item, stage), queued in an order
+// that respects every dependency, each with the segments it waits for.  Leaves
+// single_ok false (with the reason) when some item does not fit the 512-thread
+// workgroup or the LDS of one workgroup.
+constexpr int kMegaStatsPerUnit = 64, kMegaLinkPerUnit = 16, kMegaCompressPerUnit = 64;
+
+pl_status build_mega(pl_batch* b) {
+    const int n = (int)b->items.size();
+    std::vector<MegaSeg> seg;
+    std::vector<StatsArgs> st;
+    std::vector<GlrtArgs> gl;
+    std::vector<CohArgs> co;
+    std::vector<LinkArgs> li;
+    std::vector<CompressArgs> cp;
+    std::vector<int> s_stats(n, -1), s_glrt(n, -1), s_coh(n, -1), s_link(n, -1), s_comp(n, -1);
+    size_t lds = 0;
+    auto reject = [&](const char* why) {
+        b->single_ok = false;
+        b->single_why = why;
+        return PL_OK;
+    };
+    auto add = [&](int stage, int arg, int64_t blocks, int per_unit, const std::vector<int>& deps) {
+        MegaSeg m{};
+        m.stage = stage;
+        m.arg = arg;
+        m.blocks = blocks;
+        m.per_unit = per_unit;
+        m.units = (blocks + per_unit - 1) / per_unit;
+        m.ndep = 0;
+        for (int d : deps)
+            if (d >= 0) m.dep[m.ndep++] = d;
+        seg.push_back(m);
+        return (int)seg.size() - 1;
+    };
+    // Queue order: statistics and GLRT of the first level; then per level its
+    // coherence, the next level's statistics and GLRT (which depend on
+    // nothing of this level, so they fill the wait for this level's
+    // coherence to drain), linking and compression.
+    std::vector<std::pair<int, int>> order;  // (level index, stage)
+    const int nl = (int)b->level_ids.size();
+    order.push_back({0, 0});
+    order.push_back({0, 1});
+    for (int l = 0; l < nl; ++l) {
+        order.push_back({l, 2});
+        if (l + 1 < nl) {
+            order.push_back({l + 1, 0});
+            order.push_back({l + 1, 1});
+        }
+        order.push_back({l, 3});
+        order.push_back({l, 4});
+    }
+    for (const auto& [level_index, stage] : order) {
+        const int lvl = b->level_ids[level_index];
+        {
+            for (int k = 0; k < n; ++k) {
+                if (b->items[k].level != lvl) continue;
+                const ItemArgs& A = b->iargs[k];
+                if (stage == 0 && A.has_stats) {
+                    st.push_back(A.stats);
+                    s_stats[k] = add(A.stats_vec ? MS_STATS_VEC : MS_STATS_SCALAR, (int)st.size() - 1, A.stats_blocks,
+                                     kMegaStatsPerUnit, {});
+                } else if (stage == 1) {
+                    if (A.glrt.TX * A.glrt.TY > mega_threads() / 2)
+                        return reject("GLRT tile larger than half the workgroup");
+                    if (2 * A.glrt_lds > lds) lds = 2 * A.glrt_lds;  // one tile per half
+                    gl.push_back(A.glrt);
+                    s_glrt[k] = add(MS_GLRT, (int)gl.size() - 1, A.glrt_blocks, 2, {s_stats[k]});  // a tile per half
+                } else if (stage == 2) {
+                    CohArgs a = A.coh;
+                    const int nt = a.N <= 16 ? 16 : 32;
+                    int64_t blocks = 0;
+                    const size_t cl = coherence_args(&a, nt, b->split, mega_threads() / 64, 0, &blocks);
+                    if (!cl) return reject("coherence tile does not fit in LDS");
+                    if ((int64_t)a.N * (a.tile_w >> 1) > (int64_t)8 * mega_threads())
+                        return reject("coherence rows too wide for the workgroup's staging");
+                    if (cl > lds) lds = cl;
+                    co.push_back(a);
+                    std::vector<int> deps = {s_glrt[k]};
+                    const pl_batch_item& it = b->items[k];
+                    for (int d = 0; d < it.N; ++d) {
+                        const void* plane = it.planes ? (const void*)it.planes[d] : nullptr;
+                        if (!plane) continue;
+                        for (int j = 0; j < n; ++j)
+                            if (j != k && b->items[j].kappa == plane) {
+                                if (s_comp[j] < 0) return reject("an item reads the compressed SLC of a later level");
+                                deps.push_back(s_comp[j]);
+                            }
+                    }
+                    if ((int)deps.size() > kMegaMaxDeps) return reject("too many compressed SLCs from other items");
+                    s_coh[k] = add(nt == 16 ? MS_COH16 : MS_COH32, (int)co.size() - 1, blocks, 1, deps);
+                } else if (stage == 3) {
+                    const int cls = (A.link.N + 3) / 4;
+                    if (mega_link_lds(cls) > lds) lds = mega_link_lds(cls);
+                    li.push_back(A.link);
+                    s_link[k] = add(MS_LINK + cls, (int)li.size() - 1, A.link_blocks, kMegaLinkPerUnit, {s_coh[k]});
+                } else if (stage == 4 && A.has_comp) {
+                    cp.push_back(A.comp);
+                    s_comp[k] = add(MS_COMPRESS, (int)cp.size() - 1, A.comp_blocks, kMegaCompressPerUnit, {s_link[k]});
+                }
+            }
+        }
+    }
+    if (lds + 256 > max_lds_bytes()) return reject("LDS of one workgroup exceeded");
+    std::vector<int64_t> start(seg.size() + 1, 0);
+    for (size_t i = 0; i < seg.size(); ++i) start[i + 1] = start[i] + seg[i].units;
+    // one device block: counters first (zeroed once, they only grow), then the tables
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_cnt = off; off = up(off + 64 + seg.size() * 8);
+    const size_t o_seg = off; off = up(off + seg.size() * sizeof(MegaSeg));
+    const size_t o_start = off; off = up(off + start.size() * 8);
+    const size_t o_st = off; off = up(off + st.size() * sizeof(StatsArgs) + 1);
+    const size_t o_gl = off; off = up(off + gl.size() * sizeof(GlrtArgs) + 1);
+    const size_t o_co = off; off = up(off + co.size() * sizeof(CohArgs) + 1);
+    const size_t o_li = off; off = up(off + li.size() * sizeof(LinkArgs) + 1);
+    const size_t o_cp = off; off = up(off + cp.size() * sizeof(CompressArgs) + 1);
+    void* mem = nullptr;
+    pl_status r = hip_ok(hipMalloc(&mem, off), "pl_batch_plan: single-launch tables");
+    if (r != PL_OK) return r;
+    b->mega_mem = mem;
+    unsigned char* base = static_cast<unsigned char*>(mem);
+    auto put = [&](size_t o, const void* src, size_t bytes) {
+        return bytes ? hip_ok(hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice), "pl_batch_plan: table upload")
+                     : PL_OK;
+    };
+    if ((r = hip_ok(hipMemset(base + o_cnt, 0, 64 + seg.size() * 8), "pl_batch_plan: counters")) != PL_OK) return r;
+    if ((r = put(o_seg, seg.data(), seg.size() * sizeof(MegaSeg))) != PL_OK) return r;
+    if ((r = put(o_start, start.data(), start.size() * 8)) != PL_OK) return r;
+    if ((r = put(o_st, st.data(), st.size() * sizeof(StatsArgs))) != PL_OK) return r;
+    if ((r = put(o_gl, gl.data(), gl.size() * sizeof(GlrtArgs))) != PL_OK) return r;
+    if ((r = put(o_co, co.data(), co.size() * sizeof(CohArgs))) != PL_OK) return r;
+    if ((r = put(o_li, li.data(), li.size() * sizeof(LinkArgs))) != PL_OK) return r;
+    if ((r = put(o_cp, cp.data(), cp.size() * sizeof(CompressArgs))) != PL_OK) return r;
+    MegaPlan& p = b->mega;
+    p.seg = reinterpret_cast<const MegaSeg*>(base + o_seg);
+    p.seg_start = reinterpret_cast<const int64_t*>(base + o_start);
+    p.nseg = (int)seg.size();
+    p.total = start.back();
+    p.stats = reinterpret_cast<const StatsArgs*>(base + o_st);
+    p.glrt = reinterpret_cast<const GlrtArgs*>(base + o_gl);
+    p.coh = reinterpret_cast<const CohArgs*>(base + o_co);
+    p.link = reinterpret_cast<const LinkArgs*>(base + o_li);
+    p.comp = reinterpret_cast<const CompressArgs*>(base + o_cp);
+    p.queue = reinterpret_cast<unsigned long long*>(base + o_cnt);
+    p.run = reinterpret_cast<unsigned int*>(base + o_cnt + 8);
+    p.finished = reinterpret_cast<unsigned int*>(base + o_cnt + 12);
+    p.error = reinterpret_cast<unsigned int*>(base + o_cnt + 16);
+    p.done = reinterpret_cast<unsigned long long*>(base + o_cnt + 64);
+    p.spin_limit = 1u << 20;  // about a quarter of a second of sleeping per wait
+    b->mega_nseg = (int)seg.size();
+    b->mega_lds = lds;
+    if ((r = allow_dynamic_lds(mega_fn(b->split), lds)) != PL_OK) return r;
+    int per_cu = 0;
+    if ((r = hip_ok(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mega_fn(b->split), mega_threads(), lds),
+                    "pl_batch_plan: occupancy query")) != PL_OK)
+        return r;
+    if (per_cu < 1) return reject("the single-launch kernel does not fit on a compute unit");
+    b->mega_grid = (int64_t)per_cu * b->cus;
+    b->single_ok = true;
+    return PL_OK;
+}
+
 void destroy(pl_batch* b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -284,6 +472,7 @@ void destroy(pl_batch* b) {
         release(L.comp);
     }
     for (void* p : b->allocations) (void)hipFree(p);
+    if (b->mega_mem) (void)hipFree(b->mega_mem);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->own) (void)hipStreamDestroy(b->own);
@@ -347,6 +536,7 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
         if (st != PL_OK) return bail(st);
     }
     b->items.assign(items, items + n_items);
+    b->iargs.assign(n_items, ItemArgs{});
     for (int k = 0; k < n_items; ++k) b->level_ids.push_back(items[k].level);
     std::sort(b->level_ids.begin(), b->level_ids.end());
     b->level_ids.erase(std::unique(b->level_ids.begin(), b->level_ids.end()), b->level_ids.end());
@@ -385,6 +575,10 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             int64_t blocks;
             const bool vec = stats_args(t, it.first_real, it.N - it.first_real, px, m, v, &a, &blocks);
             add_member(L.stats[vec ? 1 : 0], k, a, blocks);
+            b->iargs[k].has_stats = true;
+            b->iargs[k].stats_vec = vec;
+            b->iargs[k].stats = a;
+            b->iargs[k].stats_blocks = blocks;
             mean = m;
             var = v;
         }
@@ -396,6 +590,9 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             if (!glrt_args(mean, var, g, n_eff, alpha, mask, count, nullptr, &a, &blocks, &lds))
                 return bail(fail(PL_ERR_UNSUPPORTED, "pl_batch_plan: window/stride too large for the GLRT tile"));
             add_member(L.glrt, k, a, blocks);
+            b->iargs[k].glrt = a;
+            b->iargs[k].glrt_blocks = blocks;
+            b->iargs[k].glrt_lds = lds;
             L.glrt.threads = a.TX * a.TY;  // same window and stride for every item
             L.glrt.lds = lds;
         }
@@ -413,6 +610,7 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             Group<CohArgs>& cg = L.coh[it.N <= 16 ? 0 : 1];
             cg.variant = it.N <= 16 ? 16 : 32;
             add_member(cg, k, a, 0);  // blocks set by configure_coherence
+            b->iargs[k].coh = a;
         }
         {
             const LinkArgs a = link_args(coh, it.N, P, it.ref_idx, (int)method, reinterpret_cast<float2*>(it.phasors),
@@ -420,12 +618,17 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
             Group<LinkArgs>& lg = L.link[(it.N + 3) / 4];
             lg.variant = (it.N + 3) / 4;
             add_member(lg, k, a, link_blocks(it.N, P));
+            b->iargs[k].link = a;
+            b->iargs[k].link_blocks = link_blocks(it.N, P);
         }
         if (it.kappa) {
             int64_t blocks;
             const CompressArgs a = compress_args(t, it.N, it.first_real, g, reinterpret_cast<const float2*>(it.phasors),
                                                  reinterpret_cast<float2*>(it.kappa), &blocks);
             add_member(L.comp, k, a, blocks);
+            b->iargs[k].has_comp = true;
+            b->iargs[k].comp = a;
+            b->iargs[k].comp_blocks = blocks;
         }
     }
     for (auto& L : b->levels) {
@@ -453,11 +656,24 @@ pl_status pl_batch_plan(const pl_batch_item* items, int32_t n_items, pl_window w
         if ((st = size_grid(b, L.comp, compress_batch_fn())) != PL_OK) return bail(st);
         if ((st = upload(L.comp)) != PL_OK) return bail(st);
     }
+    if ((st = build_mega(b)) != PL_OK) return bail(st);
+    b->single = b->single_ok;  // one launch per run unless it cannot be built
     if (tune) {
         // inputs written on the caller's stream are visible to the plan's stream
         st = hip_ok(hipEventRecord(b->ev_in, reinterpret_cast<hipStream_t>(stream)), "pl_batch_plan: event");
         if (st == PL_OK) st = hip_ok(hipStreamWaitEvent(b->own, b->ev_in, 0), "pl_batch_plan: event");
         if (st == PL_OK) st = autotune(b);
+        // both forms on the live inputs, for the record (pl_batch_describe)
+        if (st == PL_OK) {
+            const bool keep = b->single;
+            b->single = false;
+            st = time_ms(b->own, [&] { return enqueue_all(b, b->own); }, 2, &b->graph_ms);
+            if (st == PL_OK && b->single_ok) {
+                b->single = true;
+                st = time_ms(b->own, [&] { return enqueue_all(b, b->own); }, 2, &b->mega_ms);
+            }
+            b->single = keep;
+        }
         if (st != PL_OK) return bail(st);
     }
     *out = b;
@@ -496,6 +712,30 @@ pl_status pl_batch_destroy(pl_batch* b) {
     (void)hipStreamSynchronize(b->own);
     destroy(b);
     return PL_OK;
+}
+
+pl_status pl_batch_set_single_launch(pl_batch* b, int32_t on) {
+    PL_CHECK(b, PL_ERR_INVALID_ARG, "pl_batch_set_single_launch: NULL plan");
+    PL_CHECK(!on || b->single_ok, PL_ERR_UNSUPPORTED, "pl_batch_set_single_launch: %s", b->single_why.c_str());
+    if ((on != 0) == b->single) return PL_OK;
+    pl_status st = hip_ok(hipStreamSynchronize(b->own), "pl_batch_set_single_launch: stream");
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->single = on != 0;
+    return st;
+}
+
+pl_status pl_batch_check(pl_batch* b, pl_stream stream) {
+    PL_CHECK(b, PL_ERR_INVALID_ARG, "pl_batch_check: NULL plan");
+    pl_status st = hip_ok(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)), "pl_batch_check: stream");
+    if (st == PL_OK) st = hip_ok(hipStreamSynchronize(b->own), "pl_batch_check: stream");
+    if (st != PL_OK || !b->single_ok) return st;
+    unsigned int err = 0;
+    st = hip_ok(hipMemcpy(&err, b->mega.error, sizeof err, hipMemcpyDeviceToHost), "pl_batch_check: error word");
+    if (st == PL_OK && err) return fail(PL_ERR_STATE, "pl_batch_check: a single-launch run waited past its bound");
+    return st;
 }
 
 pl_status pl_batch_describe(const pl_batch* b, char* buf, size_t len) {
@@ -544,7 +784,13 @@ pl_status pl_batch_describe(const pl_batch* b, char* buf, size_t len) {
             s += line;
         }
     }
-    snprintf(line, sizeof line, "launches per run %d\n", launches);
+    snprintf(line, sizeof line,
+             "single launch: %s (%d segments, %lld work units, grid %lld, lds %zu), tuned %.3f ms; graph of the stage launches: tuned %.3f ms\n",
+             b->single_ok ? "available" : b->single_why.c_str(), b->mega_nseg, (long long)b->mega.total,
+             (long long)b->mega_grid, b->mega_lds, b->mega_ms, b->graph_ms);
+    s += line;
+    snprintf(line, sizeof line, "mode %s\nlaunches per run %d\n", b->single ? "single launch" : "stage launches",
+             b->single ? 1 : launches);
     s += line;
     if (s.size() + 1 > len) s.resize(len - 1);
     snprintf(buf, len, "%s", s.c_str());

@@ -3,53 +3,20 @@
 // decimation block.  HBM-bound: one thread per pixel, coalesced plane reads;
 // the phasor reads hit in cache (one block serves stride_x * stride_y pixels).
 #include "batch_device.hpp"
+#include "compress_device.hpp"
 #include "internal.hpp"
 
 namespace plk {
 namespace {
 
-constexpr int kBlock = 256;
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void compress_body(const CompressArgs& a, int64_t block_x, int64_t y) {
-    const PlaneTable& t = a.t;
-    const Geometry& g = a.g;
-    const int N = a.N, first_real = a.first_real;
-    const float2* __restrict__ ph = a.ph;
-    float2* __restrict__ kappa = a.kappa;
-    const int64_t x = block_x * kBlock + threadIdx.x;
-    if (x >= g.C) return;
-    int64_t by = y / g.sy, bx = x / g.sx;
-    by = by < g.oR - 1 ? by : g.oR - 1;
-    bx = bx < g.oC - 1 ? bx : g.oC - 1;
-    const int64_t opix = g.oR * g.oC;
-    const int64_t b = by * g.oC + bx;
-    const int64_t p = y * g.C + x;
-    float re = 0.f, im = 0.f;
-    for (int i = first_real; i < N; ++i) {
-        const f32x2 z = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(t.p[i]) + p);
-        float2 w = ph[(int64_t)i * opix + b];
-        // conj(w) * z
-        re = fmaf(w.x, z.x, fmaf(w.y, z.y, re));
-        im = fmaf(w.x, z.y, fmaf(-w.y, z.x, im));
-    }
-    if (a.rot >= 0) {  // times phasor rot: the sum re-referenced to image rot
-        const float2 w = ph[(int64_t)a.rot * opix + b];
-        const float r2 = re * w.x - im * w.y;
-        im = re * w.y + im * w.x;
-        re = r2;
-    }
-    kappa[p] = make_float2(re, im);
-}
-
-__global__ __launch_bounds__(kBlock) void compress_kernel(CompressArgs a) { compress_body(a, blockIdx.x, blockIdx.y); }
+__global__ __launch_bounds__(kBlock) void compress_kernel(CompressArgs a) { compress_body(a, blockIdx.x, blockIdx.y, threadIdx.x); }
 
 __global__ __launch_bounds__(kBlock) void compress_batch(BatchRange<CompressArgs> r) {
     for (int64_t b = blockIdx.x; b < r.total; b += gridDim.x) {
         const int k = batch_item(r.starts, r.n, b);
         const CompressArgs& a = r.items[k];
         const int64_t local = b - r.starts[k];
-        compress_body(a, local % a.gx, local / a.gx);
+        compress_body(a, local % a.gx, local / a.gx, threadIdx.x);
     }
 }
 

@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "internal.hpp"
+#include "lanes.hpp"
 
 namespace plk {
 namespace {
@@ -28,20 +29,6 @@ constexpr float kTol2 = 4e-12f;  // squared change of the unit iterate at conver
 constexpr int kMaxIter = 96;
 constexpr float kRefineRate = 0.5f;           // refine the shift when |dx| shrinks slower
 __constant__ float kRefine[3] = {1.f, 2.f, 4.f};  // margins of the refined shifts, in residuals
-constexpr int kBlock = 256;
-
-__device__ __forceinline__ int lane_id() {
-    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0));
-}
-
-// Orders this wavefront's LDS stores before its later LDS loads of words
-// that other lanes of the wavefront wrote (release, wave barrier, acquire).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Opaque copies of an integer: offsets formed from them are neither merged
 // with earlier ones nor hoisted above this point (out of a loop), so loads
 // through them are not hoisted either (which would keep the loaded values

@@ -14,81 +14,11 @@
 #include <cmath>
 
 #include "batch_device.hpp"
+#include "glrt_device.hpp"
 #include "internal.hpp"
 
 namespace plk {
 namespace {
-
-constexpr double kRecheckRel = 1e-8;
-constexpr double kBand = 1e-9;
-
-__device__ void glrt_body(const GlrtArgs& a, int64_t bx, int64_t by, double* s_tile) {
-    const Geometry& g = a.g;
-    const int64_t oy0 = by * a.TY, ox0 = bx * a.TX;
-    const int64_t y0 = oy0 * g.sy + g.sy / 2 - g.hy;
-    const int64_t x0 = ox0 * g.sx + g.sx / 2 - g.hx;
-    const int nt = a.tw * a.th;
-    for (int i = threadIdx.x; i < nt; i += blockDim.x) {
-        int ly = i / a.tw, lx = i - ly * a.tw;
-        int64_t y = y0 + ly, x = x0 + lx;
-        double s = __builtin_nan("");
-        if (y >= 0 && y < g.R && x >= 0 && x < g.C) {
-            int64_t p = y * g.C + x;
-            double m = a.mean[p], v = a.var[p];
-            double sv = 0.5 * fma(m, m, v);
-            if (sv > 0.0 && sv <= 1.7976931348623157e308) s = sv;
-        }
-        s_tile[i] = s;
-    }
-    __syncthreads();
-
-    const int ly = threadIdx.x / a.TX, lx = threadIdx.x - ly * a.TX;
-    const int64_t oy = oy0 + ly, ox = ox0 + lx;
-    if (ly >= a.TY || oy >= g.oR || ox >= g.oC) return;
-    const double* row0 = s_tile + (ly * g.sy) * a.tw + lx * g.sx;
-    const double sp = row0[g.hy * a.tw + g.hx];
-    const bool pvalid = sp == sp;
-    const double lo = a.rlo * sp, hi = a.rhi * sp;
-    const double lo_tol = kRecheckRel * lo, hi_tol = kRecheckRel * hi;
-    const int64_t pix = oy * g.oC + ox;
-    uint32_t* out = a.mask + pix * g.nw;
-    uint32_t word = 0;
-    int bit = 0, wi = 0, cnt = 0;
-    unsigned long long band = 0, rechecks = 0;
-    for (int dy = 0; dy < g.wy; ++dy) {
-        const double* row = row0 + dy * a.tw;
-        for (int dx = 0; dx < g.wx; ++dx) {
-            const double sq = row[dx];
-            bool ok;
-            if (dy == g.hy && dx == g.hx) {
-                ok = true;
-            } else if (!pvalid) {
-                ok = false;
-            } else {
-                ok = (sq >= lo) && (sq <= hi);  // false for NaN
-                if (fabs(sq - hi) <= hi_tol || fabs(sq - lo) <= lo_tol) {
-                    const double t = 2.0 * a.n * (2.0 * log((sp + sq) * 0.5) - log(sp) - log(sq));
-                    ok = t <= a.thr;
-                    ++rechecks;
-                    if (fabs(t - a.thr) < kBand) ++band;
-                }
-            }
-            word |= (uint32_t)ok << bit;
-            cnt += ok;
-            if (++bit == 32) {
-                out[wi++] = word;
-                word = 0;
-                bit = 0;
-            }
-        }
-    }
-    if (bit) out[wi] = word;
-    a.count[pix] = (uint16_t)cnt;
-    if (a.counters && (band | rechecks)) {
-        atomicAdd(a.counters + PL_CNT_GLRT_BAND, band);
-        atomicAdd(a.counters + PL_CNT_GLRT_RECHECK, rechecks);
-    }
-}
 
 // chi-square (1 dof) upper quantile: thr = z^2 with erfc(z / sqrt(2)) = alpha,
 // found by bisection on the monotone erfc in long double.
@@ -104,7 +34,7 @@ double chi2_1_isf(double alpha) {
 
 __global__ __launch_bounds__(256) void glrt_kernel(GlrtArgs a) {
     extern __shared__ double s_tile[];
-    glrt_body(a, blockIdx.x, blockIdx.y, s_tile);
+    glrt_body(a, blockIdx.x, blockIdx.y, s_tile, threadIdx.x, blockDim.x);
 }
 
 __global__ __launch_bounds__(256) void glrt_batch(BatchRange<GlrtArgs> r) {
@@ -113,7 +43,7 @@ __global__ __launch_bounds__(256) void glrt_batch(BatchRange<GlrtArgs> r) {
         const int k = batch_item(r.starts, r.n, b);
         const GlrtArgs& a = r.items[k];
         const int64_t local = b - r.starts[k];
-        glrt_body(a, local % a.gx, local / a.gx, s_tile);
+        glrt_body(a, local % a.gx, local / a.gx, s_tile, threadIdx.x, blockDim.x);
         __syncthreads();  // the tile is refilled by the next block
     }
 }

@@ -174,4 +174,44 @@ pl_status launch_coherence_batch(const BatchRange<CohArgs>& r, int nt, bool spli
 pl_status launch_phase_link_batch(const BatchRange<LinkArgs>& r, int N_class, int64_t grid, hipStream_t s);
 pl_status launch_compress_batch(const BatchRange<CompressArgs>& r, int64_t grid, hipStream_t s);
 
+// ---- the whole batched run as one persistent launch: a queue of work units
+// in dependency order (stage segments of every item), each segment's
+// completions counted in device memory, every wait bounded
+enum MegaStage {
+    MS_STATS_VEC = 0, MS_STATS_SCALAR, MS_GLRT, MS_COH16, MS_COH32,
+    MS_LINK = 8,                  // + linking class (N + 3) / 4, 1..8
+    MS_COMPRESS = MS_LINK + 9,
+};
+constexpr int kMegaMaxDeps = 8;
+struct MegaSeg {
+    int stage;        // MegaStage
+    int arg;          // index into the stage's argument table
+    int64_t blocks;   // blocks of the stage's own kernel for this item
+    int per_unit;     // of those, per work unit
+    int64_t units;
+    int ndep;
+    int dep[kMegaMaxDeps];  // earlier segments that must be complete first
+};
+struct MegaPlan {
+    const MegaSeg* seg;
+    const int64_t* seg_start;  // nseg + 1 prefix sums of units
+    int nseg;
+    int64_t total;             // work units per run
+    const StatsArgs* stats;
+    const GlrtArgs* glrt;
+    const CohArgs* coh;
+    const LinkArgs* link;
+    const CompressArgs* comp;
+    unsigned long long* queue;  // units handed out, over all runs
+    unsigned long long* done;   // [nseg] completed units, over all runs
+    unsigned int* run;          // completed runs
+    unsigned int* finished;     // workgroups finished, over all runs
+    unsigned int* error;        // set when a wait exceeded spin_limit
+    unsigned int spin_limit;
+};
+int mega_threads();
+const void* mega_fn(bool split);
+size_t mega_link_lds(int N_class);  // LDS of one work unit of a linking class
+pl_status launch_mega(const MegaPlan& p, bool split, size_t lds, int64_t grid, hipStream_t s);
+
 }  // namespace plk

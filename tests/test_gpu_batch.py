@@ -1,5 +1,6 @@
 """Batched, graph-replayed runs over mini-stacks with uneven N (the k-th
-mini-stack of a burst carries k compressed SLCs, so N = 15 + k) against the
+mini-stack of a burst carries k compressed SLCs, so N = 15 + k), as one
+persistent launch (the default) and as one launch per stage, against the
 single-call entry points (bit-identical: the same kernel bodies) and, item by
 item, against the FP64 oracle."""
 import numpy as np
@@ -143,8 +144,28 @@ def test_chained_sequence_matches_sequential_driver(gpu_lib, prec):
                               n_eff=float((K + 1) * M), kappa=kappas[bi, k], level=k))
     b = plink.Batch(items, bursts[0][0].window, precision=prec, autotune=True)
     print(b.describe(), flush=True)
+    assert "mode single launch" in b.describe() and "launches per run 1" in b.describe()
+    b.run()
+    b.check()  # no wait of the single launch ran past its bound
+    torch.cuda.synchronize()
+    single = [(p.clone(), f.clone()) for p, f in zip(b.phasors, b.flags)]
+    single_kappa = {key: v.clone() for key, v in kappas.items()}
+    # the same plan as one launch per stage and kernel variant: the same bits
+    b.set_single_launch(False)
     b.run()
     torch.cuda.synchronize()
+    assert "mode stage launches" in b.describe()
+    for i, (p, f) in enumerate(single):
+        assert torch.equal(b.phasors[i], p) and torch.equal(b.flags[i], f), f"item {i}: single launch differs"
+    for key, v in single_kappa.items():
+        assert torch.equal(kappas[key], v), f"kappa {key}: single launch differs"
+    b.set_single_launch(True)
+    for _ in range(2):  # replays of the single-launch graph keep the counters consistent
+        b.run()
+    b.check()
+    torch.cuda.synchronize()
+    for i, (p, f) in enumerate(single):
+        assert torch.equal(b.phasors[i], p) and torch.equal(b.flags[i], f), f"item {i}: replay differs"
     it = iter(range(len(items)))
     for bi, (wl, z) in enumerate(bursts):
         M = wl.n_new
