@@ -437,9 +437,15 @@ pl_status pl_batch_describe(const pl_batch* b, char* buf, size_t len);
  * gives the reason: a tile that does not fit one 512-thread workgroup). */
 pl_status pl_batch_set_single_launch(pl_batch* b, int32_t on);
 /* Synchronises `stream` and the plan's stream; PL_ERR_STATE if a
- * single-launch run ever waited past its bound (about 0.25 s per wait;
- * the run then completed without its ordering guarantee). */
+ * single-launch run since the previous check waited past its bound (about
+ * 0.25 s per wait; the run then completed without its ordering guarantee,
+ * so its outputs are not to be used). */
 pl_status pl_batch_check(pl_batch* b, pl_stream stream);
+/* Sets the bound of every wait of the single launch, in sleep rounds of about
+ * 0.2 us (default 2^20); drops a captured graph.  A bound of 0 makes every
+ * wait give up at once: the run still ends and pl_batch_check reports it,
+ * which is how the failure path is tested without stalling a GPU. */
+pl_status pl_batch_set_wait_limit(pl_batch* b, uint32_t spins);
 
 #ifdef __cplusplus
 }

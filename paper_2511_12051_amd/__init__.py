@@ -119,6 +119,7 @@ _SIGNATURES = {
     "pl_batch_describe": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "pl_batch_set_single_launch": (ctypes.c_int, [_P, ctypes.c_int32]),
     "pl_batch_check": (ctypes.c_int, [_P, ctypes.c_void_p]),
+    "pl_batch_set_wait_limit": (ctypes.c_int, [_P, ctypes.c_uint32]),
     "pl_seq_create": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(_P)]),
     "pl_seq_workspace_size": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.POINTER(ctypes.c_size_t)]),
     "pl_seq_create_in": (ctypes.c_int, [ctypes.POINTER(_SeqParams), ctypes.c_void_p, ctypes.c_size_t,
@@ -577,6 +578,11 @@ class Batch:
         (the default when the plan supports it); False: one launch per stage
         and kernel variant."""
         _check(load().pl_batch_set_single_launch(self._h, int(bool(on))), "Batch.set_single_launch")
+
+    def set_wait_limit(self, spins: int):
+        """Bound of each wait of the single launch (sleep rounds); 0 makes
+        every wait give up at once (for tests of the failure path)."""
+        _check(load().pl_batch_set_wait_limit(self._h, int(spins)), "Batch.set_wait_limit")
 
     def check(self):
         """Synchronises and raises if a single-launch run waited past its bound."""

@@ -734,7 +734,22 @@ pl_status pl_batch_check(pl_batch* b, pl_stream stream) {
     if (st != PL_OK || !b->single_ok) return st;
     unsigned int err = 0;
     st = hip_ok(hipMemcpy(&err, b->mega.error, sizeof err, hipMemcpyDeviceToHost), "pl_batch_check: error word");
-    if (st == PL_OK && err) return fail(PL_ERR_STATE, "pl_batch_check: a single-launch run waited past its bound");
+    if (st == PL_OK && err) {
+        (void)hipMemset(b->mega.error, 0, sizeof err);  // reported once
+        return fail(PL_ERR_STATE, "pl_batch_check: a single-launch run waited past its bound");
+    }
+    return st;
+}
+
+pl_status pl_batch_set_wait_limit(pl_batch* b, uint32_t spins) {
+    PL_CHECK(b, PL_ERR_INVALID_ARG, "pl_batch_set_wait_limit: NULL plan");
+    PL_CHECK(b->single_ok, PL_ERR_UNSUPPORTED, "pl_batch_set_wait_limit: %s", b->single_why.c_str());
+    pl_status st = hip_ok(hipStreamSynchronize(b->own), "pl_batch_set_wait_limit: stream");
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);  // the limit is a launch argument
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->mega.spin_limit = spins;
     return st;
 }
 

@@ -179,3 +179,37 @@ def test_chained_sequence_matches_sequential_driver(gpu_lib, prec):
             assert torch.equal(kappas[bi, k], kap), f"burst {bi} mini-stack {k} kappa"
         seq.close()
     b.close()
+
+
+def test_single_launch_wait_bound_reports_and_recovers(gpu_lib):
+    """The failure path of the single launch, forced from the host: with a
+    wait bound of 0 every dependency wait gives up at once, the launch still
+    ends and check() reports it (the outputs of that run are not used); with
+    the bound restored the run matches the stage launches bit for bit."""
+    plink = gpu_lib
+    wl = synth.crop("sequential", 96, 198)
+    z = synth.make_sequence(wl, seed=90, ministacks=3).cuda()
+    M = wl.n_new
+    kap = [torch.empty((wl.R, wl.C), dtype=torch.complex64, device="cuda") for _ in range(3)]
+    items = []
+    for k in range(3):
+        K = min(k, 2)
+        items.append(dict(planes=kap[k - K:k] + [z[k * M + m] for m in range(M)], first_real=K, ref=max(0, K - 1),
+                          kappa=kap[k], level=k))
+    b = plink.Batch(items, wl.window, precision="bf16")
+    b.set_single_launch(False)
+    b.run()
+    torch.cuda.synchronize()
+    ref = [p.clone() for p in b.phasors]
+    b.set_single_launch(True)
+    b.set_wait_limit(0)
+    b.run()
+    with pytest.raises(plink.PlinkError):
+        b.check()
+    b.set_wait_limit(1 << 20)
+    b.run()
+    b.check()
+    torch.cuda.synchronize()
+    for i, p in enumerate(ref):
+        assert torch.equal(b.phasors[i], p), f"item {i}"
+    b.close()
