@@ -23,9 +23,13 @@ constexpr int link_lds_bytes() {
 }
 
 // Pixel block `block` (kBlock / 64 wavefronts of four pixels); tid is the
-// thread's index in the block and lds the block's link_lds_bytes() of LDS.
+// thread's index in the block (its wavefront tid / 64 picks the four
+// pixels) and lds the block's link_lds_bytes() of LDS.  lds_wave (>= 0)
+// names the wavefront slot of lds this wavefront uses instead of tid / 64,
+// for callers whose wavefronts take the pixel groups of a block in any order.
 template <int R, int NJ>
-__device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int tid, float2* lds) {
+__device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int tid, float2* lds,
+                                          int lds_wave = -1) {
     constexpr int GPW = 4;  // 16-lane groups (pixels) per wavefront
     // NJ >= N columns are stored and updated per row (N rounded up to a
     // multiple of 4); lane l of a group holds rows l and, for R = 2, l + 16.
@@ -43,6 +47,8 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
     const int l = lane & 15;
     const int grp = lane >> 4;
     const int wave = tid >> 6;
+    const int slot = lds_wave >= 0 ? lds_wave : wave;  // LDS slot of this wavefront
+    const int stid = (slot << 6) | (tid & 63);
 
     const int N = opaque_uniform(__builtin_amdgcn_readfirstlane(a.N));
     const int64_t pix = (block * (kBlock / 64) + wave) * GPW + grp;
@@ -125,7 +131,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
             x[r].y *= q;
         }
     }
-    const Tri tri{lds + wave * Tri::WAVE_ENTRIES, grp, l, N, lds + (kBlock / 64) * Tri::WAVE_ENTRIES + wave * XS};
+    const Tri tri{lds + slot * Tri::WAVE_ENTRIES, grp, l, N, lds + (kBlock / 64) * Tri::WAVE_ENTRIES + slot * XS};
     if constexpr (R == 2) {
         // C's upper triangle goes to LDS now; B is formed there after step 1.
         // The fence orders these stores after the previous pixel's reads of
@@ -158,7 +164,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
         const float2* src2 = src + opaque_int(0);
         const float2* mat2 = mat + opaque_int(0);
         const int i0 = min(l, N - 1);
-        float2* bme = lds + tid;  // element j at bme[j * kBlock]
+        float2* bme = lds + stid;  // element j at bme[j * kBlock]
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             float2 cl;
@@ -212,7 +218,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
         float2 brow[R][NJ];
         if constexpr (R == 1) {
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) brow[0][j] = lds[tid + j * kBlock];
+            for (int j = 0; j < NJ; ++j) brow[0][j] = lds[stid + j * kBlock];
         } else {
             tri.load(brow, true);
         }
@@ -235,7 +241,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
     int it, retries;
     float2 bx[R];
     if constexpr (R == 1) {
-        const BRowLds<16, NJ> bv{lds + tid, nullptr, l};
+        const BRowLds<16, NJ> bv{lds + stid, nullptr, l};
         eig_min_r<16, 1, NJ>(m, bv, bnorm2, mu, !invalid, N, l, nullptr, nullptr, nullptr, x, conv, it, retries);
         bv.apply(x, bx);
     } else {

@@ -29,15 +29,28 @@ namespace {
 
 constexpr int kMegaThreads = 512;
 
+// The unit's pixel groups (four pixels per wavefront, four per block) go to
+// the workgroup's wavefronts one at a time from a counter in LDS, so a
+// wavefront that finishes early takes the next group: the unit then ends
+// with at most one group of imbalance rather than a wavefront's whole share.
 template <int R, int NJ>
-__device__ __forceinline__ void mega_link(const LinkArgs& a, int64_t b0, int64_t b1, uint32_t* lds) {
-    const int sub = threadIdx.x / kBlock, tid = threadIdx.x % kBlock;
-    float2* l = reinterpret_cast<float2*>(lds) + sub * (link_lds_bytes<R, NJ>() / 8);
-    for (int64_t b = b0 + sub; b < b1; b += 2) link_body<R, NJ>(a, b, tid, l);
+__device__ __forceinline__ void mega_link(const LinkArgs& a, int64_t b0, int64_t b1, uint32_t* lds, int* next) {
+    const int phys = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float2* l = reinterpret_cast<float2*>(lds) + (phys >> 2) * (link_lds_bytes<R, NJ>() / 8);
+    const int groups = (int)(b1 - b0) * (kBlock / 64);
+    for (;;) {
+        int g = 0;
+        if (lane == 0) g = atomicAdd(next, 1);
+        g = __builtin_amdgcn_readfirstlane(g);
+        if (g >= groups) break;
+        const int64_t b = b0 + g / (kBlock / 64);
+        link_body<R, NJ>(a, b, ((g % (kBlock / 64)) << 6) | lane, l, phys & 3);
+    }
 }
 
 template <bool SPLIT>
-__device__ __forceinline__ void mega_unit(const MegaPlan& p, const MegaSeg& S, int64_t unit, uint32_t* lds) {
+__device__ __forceinline__ void mega_unit(const MegaPlan& p, const MegaSeg& S, int64_t unit, uint32_t* lds,
+                                          int* next) {
     const int64_t b0 = unit * S.per_unit;
     const int64_t b1 = b0 + S.per_unit < S.blocks ? b0 + S.per_unit : S.blocks;
     const int sub = threadIdx.x / kBlock, tid = threadIdx.x % kBlock;
@@ -93,12 +106,12 @@ __device__ __forceinline__ void mega_unit(const MegaPlan& p, const MegaSeg& S, i
         default: {
             const LinkArgs& a = p.link[S.arg];
             switch (S.stage - MS_LINK) {
-                case 1: case 2: case 3: mega_link<1, 12>(a, b0, b1, lds); break;
-                case 4: mega_link<1, 16>(a, b0, b1, lds); break;
-                case 5: mega_link<2, 20>(a, b0, b1, lds); break;
-                case 6: mega_link<2, 24>(a, b0, b1, lds); break;
-                case 7: mega_link<2, 28>(a, b0, b1, lds); break;
-                default: mega_link<2, 32>(a, b0, b1, lds); break;
+                case 1: case 2: case 3: mega_link<1, 12>(a, b0, b1, lds, next); break;
+                case 4: mega_link<1, 16>(a, b0, b1, lds, next); break;
+                case 5: mega_link<2, 20>(a, b0, b1, lds, next); break;
+                case 6: mega_link<2, 24>(a, b0, b1, lds, next); break;
+                case 7: mega_link<2, 28>(a, b0, b1, lds, next); break;
+                default: mega_link<2, 32>(a, b0, b1, lds, next); break;
             }
         }
     }
@@ -110,6 +123,7 @@ void batch_mega(MegaPlan p) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     __shared__ long long s_unit;
     __shared__ int s_seg;
+    __shared__ int s_next;  // pixel groups of a linking unit handed out so far
     const unsigned run = __hip_atomic_load(p.run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long base = (unsigned long long)run * (unsigned long long)(p.total + gridDim.x);
     int cur = -1, pend_seg = -1;  // meaningful in thread 0
@@ -150,13 +164,14 @@ void batch_mega(MegaPlan p) {
             }
             s_unit = (long long)u;
             s_seg = sg;
+            s_next = 0;
         }
         __syncthreads();
         const int sg = s_seg;
         const long long u = s_unit;
         if (sg < 0) break;
         cur = sg;
-        mega_unit<SPLIT>(p, p.seg[sg], u - p.seg_start[sg], lds);
+        mega_unit<SPLIT>(p, p.seg[sg], u - p.seg_start[sg], lds, &s_next);
         __syncthreads();  // the unit is done; s_unit and s_seg may be rewritten
         if (threadIdx.x == 0) {
             pend_seg = sg;
