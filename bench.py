@@ -366,9 +366,12 @@ def measure(torch, plink, wl, stack, prec, steps, warmup, skip_fused=False):
                                   "shift_retries_per_pixel": cnt["shift_retry"] / P,
                                   "not_converged": cnt["not_converged"], "glrt_band_pairs": cnt["glrt_band"]}}
     # the same step with coherence and linking fused through a bounded buffer
-    # of packed coherence bands (at most 1 GiB, whole rows)
+    # of packed coherence bands (whole rows)
     row, full = plink.phase_link_fused_workspace(wl.N, wl.R, wl.C, wl.window)
-    ws = torch.empty((min(full, max(row, (1 << 30) // row * row)),), dtype=torch.uint8, device=stack.device)
+    # at most 16 GiB of band buffer: every output row of the 4096x16384 N=25
+    # workload (9.7 GB of packed coherence) fits in one band
+    cap = int(os.environ.get("PLINK_FUSED_BUFFER_GIB", "16")) << 30
+    ws = torch.empty((min(full, max(row, cap // row * row)),), dtype=torch.uint8, device=stack.device)
     tf = time_steps(torch, lambda: path.step_fused(ws), steps, warmup)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     m = path.glrt(path.stats())
