@@ -43,6 +43,14 @@ __device__ __forceinline__ int opaque_uniform(int v) {
     return v;
 }
 
+// Marks four loaded values as used here.  Loads whose values are first used
+// under a select can be turned into a branch per load (each then waits for
+// its data before the next is issued); placed after a run of loads, this
+// keeps them unconditional and back to back, with one wait before it.
+__device__ __forceinline__ void issued(float2& a, float2& b, float2& c, float2& d) {
+    asm volatile("" : "+v"(a.x), "+v"(a.y), "+v"(b.x), "+v"(b.y), "+v"(c.x), "+v"(c.y), "+v"(d.x), "+v"(d.y));
+}
+
 // Reductions over the NP lanes of a group.  Within a row of 16 lanes they use
 // DPP lane permutations (quad swaps, half-row and row mirrors), so no LDS
 // round trip is needed; wider groups add exchanges between rows.
@@ -771,13 +779,19 @@ struct BTriLds {
     // first and read with one load (selecting between two loaded values
     // lets the compiler put each load in a branch of its own, with a wait).
     template <int J>
-    __device__ __forceinline__ float2 get(int ub, int lb, int ll, int r, int n) const {
+    __device__ __forceinline__ int offset(int ub, int lb, int ll, int r) const {
+        return J >= ll + 16 * r ? ub + J * GPW : lb + cj(J) * GPW;  // entry (i, J), or (J, i) below the diagonal
+    }
+    // B[i][J] from the stored entry v read at offset<J>()
+    template <int J>
+    __device__ __forceinline__ float2 entry(float2 v, int ll, int r, int n) const {
         const int i = ll + 16 * r;
-        const bool up = J >= i;
-        const int o = up ? ub + J * GPW : lb + cj(J) * GPW;  // entry (i, J), or (J, i) below the diagonal
-        const float2 v = w[o];
-        const float2 h = make_float2(v.x, up ? v.y : -v.y);
+        const float2 h = make_float2(v.x, J >= i ? v.y : -v.y);
         return (i < n && J < n) ? h : make_float2(0.f, 0.f);
+    }
+    template <int J>
+    __device__ __forceinline__ float2 get(int ub, int lb, int ll, int r, int n) const {
+        return entry<J>(w[offset<J>(ub, lb, ll, r)], ll, r, n);
     }
     // offset of entry (i, J) if this lane owns it (J >= i, both < N), else the sink
     template <int J>
@@ -806,21 +820,38 @@ struct BTriLds {
             load_steps<0>(m, ub, lb, ll, n);
         }
     }
+    // Columns J .. J + 3: the eight entries are loaded before any is used, so
+    // that one wait covers them (used one by one, each load would wait for
+    // its data before the next is issued); at most four columns in flight,
+    // since all of them would need 8 NJ registers next to the factorisation.
     template <int J>
     __device__ __forceinline__ void apply_steps(const int (&ub)[2], const int (&lb)[2], int ll, int n,
                                                 const float2 (&x)[2], float2 (&y)[2]) const {
         if constexpr (J < NJ) {
-            const float vx = rowcast<J % 16>(x[J / 16].x), vy = rowcast<J % 16>(x[J / 16].y);
+            float2 b[4][2];
+            [&]<int... Q>(std::integer_sequence<int, Q...>) {
+                ((b[Q][0] = w[offset<J + Q>(ub[0], lb[0], ll, 0)], b[Q][1] = w[offset<J + Q>(ub[1], lb[1], ll, 1)]),
+                 ...);
+            }(std::make_integer_sequence<int, 4>{});
+            issued(b[0][0], b[0][1], b[1][0], b[1][1]);
+            issued(b[2][0], b[2][1], b[3][0], b[3][1]);
+            [&]<int... Q>(std::integer_sequence<int, Q...>) {
+                ((b[Q][0] = entry<J + Q>(b[Q][0], ll, 0, n), b[Q][1] = entry<J + Q>(b[Q][1], ll, 1, n)), ...);
+            }(std::make_integer_sequence<int, 4>{});
+            [&]<int... Q>(std::integer_sequence<int, Q...>) {
+                auto col = [&](auto qc) __attribute__((always_inline)) {
+                    constexpr int q = decltype(qc)::value;
+                    const float vx = rowcast<(J + q) % 16>(x[(J + q) / 16].x), vy = rowcast<(J + q) % 16>(x[(J + q) / 16].y);
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const float2 b = get<J>(ub[r], lb[r], ll, r, n);
-                y[r].x = fmaf(b.x, vx, fmaf(-b.y, vy, y[r].x));
-                y[r].y = fmaf(b.x, vy, fmaf(b.y, vx, y[r].y));
-            }
-            // at most four columns of loads in flight: issued all at once they
-            // would need 8 NJ registers next to the factorisation in m
-            if constexpr (J % 4 == 3) __builtin_amdgcn_sched_barrier(0);
-            apply_steps<J + 1>(ub, lb, ll, n, x, y);
+                    for (int r = 0; r < 2; ++r) {
+                        y[r].x = fmaf(b[q][r].x, vx, fmaf(-b[q][r].y, vy, y[r].x));
+                        y[r].y = fmaf(b[q][r].x, vy, fmaf(b[q][r].y, vx, y[r].y));
+                    }
+                };
+                (col(std::integral_constant<int, Q>{}), ...);
+            }(std::make_integer_sequence<int, 4>{});
+            __builtin_amdgcn_sched_barrier(0);
+            apply_steps<J + 4>(ub, lb, ll, n, x, y);
         }
     }
     // y = B x for this lane's two rows
@@ -929,15 +960,24 @@ template <int NJ>
 __device__ __forceinline__ void acc_load(const BTriLds<NJ>& tri, int g, float mu, int N, int lane, f32x16& ar,
                                          f32x16& ai) {
     const int c = lane & 31, h = lane >> 5;
+    float2 b[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         const int i = acc_row(v, h);
-        const int lo = i < c ? i : c, hi = i < c ? c : i;
+        // entry (min, max) of (i, c), clamped into the triangle (no select:
+        // a selected offset becomes a branch); unused outside N x N
+        const int lo = min(min(i, c), NJ - 1), hi = min(max(i, c), NJ - 1);
+        const int e = ((lo * (2 * NJ - 1 - lo)) >> 1) + hi;
+        b[v] = tri.w[e * BTriLds<NJ>::GPW + g];
+    }
+#pragma unroll
+    for (int v = 0; v < 16; v += 4) issued(b[v], b[v + 1], b[v + 2], b[v + 3]);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = acc_row(v, h);
         const bool in = i < N && c < N;
-        const int e = in ? (lo * (2 * NJ - lo - 1)) / 2 + hi : 0;
-        const float2 b = tri.w[e * BTriLds<NJ>::GPW + g];
-        ar[v] = in ? b.x - (i == c ? mu : 0.f) : 0.f;
-        ai[v] = in ? (i > c ? -b.y : b.y) : 0.f;
+        ar[v] = in ? b[v].x - (i == c ? mu : 0.f) : 0.f;
+        ai[v] = in ? (i > c ? -b[v].y : b[v].y) : 0.f;
     }
 }
 

@@ -190,26 +190,42 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
         for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int j = 0; j < NJ; ++j) gf[r][j] = (float)gi[r][j];
-        [&]<int... J>(std::integer_sequence<int, J...>) {
-            auto one = [&](auto jc, int r) __attribute__((always_inline)) {
-                constexpr int j = decltype(jc)::value;
-                const int o = tri.template own<j>(ub[r], l, r, N);
-                const float2 cv = tri.w[o];
-                const float gv = gf[r][j];
-                const float2 v = use_evd ? make_float2(-cv.x, -cv.y) : make_float2(gv * cv.x, gv * cv.y);
-                tri.w[o] = v;
-                const float wgt = (o == tri.sink()) ? 0.f : (j == l + 16 * r ? 1.f : 2.f);
-                bnorm2 = fmaf(wgt * v.x, v.x, fmaf(wgt * v.y, v.y, bnorm2));
-            };
-            // at most four columns of loads in flight
-            auto four = [&](auto jc) __attribute__((always_inline)) {
-                constexpr int j = decltype(jc)::value;
+        // four columns at a time: their eight entries are loaded before any
+        // is rewritten (a load after a store to an offset the compiler cannot
+        // tell apart would wait for its data entry by entry; only non-owned
+        // entries share an offset, the sink, whose contents are never used)
+        [&]<int... K>(std::integer_sequence<int, K...>) {
+            auto four = [&](auto kc) __attribute__((always_inline)) {
+                constexpr int j0 = 4 * decltype(kc)::value;
+                int o[4][2];
+                float2 cv[4][2];
+                [&]<int... Q>(std::integer_sequence<int, Q...>) {
+                    ((o[Q][0] = tri.template own<j0 + Q>(ub[0], l, 0, N),
+                      o[Q][1] = tri.template own<j0 + Q>(ub[1], l, 1, N)), ...);
+                }(std::make_integer_sequence<int, 4>{});
 #pragma unroll
-                for (int r = 0; r < R; ++r) one(jc, r);
-                if constexpr (j % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) cv[q][r] = tri.w[o[q][r]];
+                issued(cv[0][0], cv[0][1], cv[1][0], cv[1][1]);
+                issued(cv[2][0], cv[2][1], cv[3][0], cv[3][1]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int r = 0; r < 2; ++r) {
+                        const int j = j0 + q;
+                        const float gv = gf[r][j];
+                        const float2 v = use_evd ? make_float2(-cv[q][r].x, -cv[q][r].y)
+                                                 : make_float2(gv * cv[q][r].x, gv * cv[q][r].y);
+                        tri.w[o[q][r]] = v;
+                        const float wgt = (o[q][r] == tri.sink()) ? 0.f : (j == l + 16 * r ? 1.f : 2.f);
+                        bnorm2 = fmaf(wgt * v.x, v.x, fmaf(wgt * v.y, v.y, bnorm2));
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
             };
-            (four(std::integral_constant<int, J>{}), ...);
-        }(std::make_integer_sequence<int, NJ>{});
+            (four(std::integral_constant<int, K>{}), ...);
+        }(std::make_integer_sequence<int, NJ / 4>{});
         wave_sync();  // B's triangle is read across lanes from here on
     }
     float mu = 0.99f;
