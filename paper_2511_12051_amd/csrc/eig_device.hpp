@@ -88,21 +88,18 @@ __device__ __forceinline__ bool gany(bool p, int grp) {
     return (b & m) != 0;
 }
 
-// |z| of an FP32 complex value to about 1e-14 relative, without the FP64
-// square-root sequence: exact sum of squares in FP64, an FP32 reciprocal
-// square root as seed and one Newton step in FP64 (the seed's 2^-23 relative
-// error becomes ~1e-14).  Sums of squares outside [1e-30, 1e30] are scaled
-// by an exact power of two into the range of the FP32 seed (every square of
-// an FP32 value lands there after scaling); there is no branch, so the
-// callers' conversions of whole rows stay straight-line code.
+// |z| of an FP32 complex value to about 2e-14 relative, without the FP64
+// square-root sequence: the sum of squares in FP64 (the products are exact),
+// the hardware FP64 reciprocal square root (about 2^-23 relative error) as a
+// seed, and one Newton step for the square root, s (1 - (x y^2 - 1) / 2),
+// whose error is 1.5 times the seed's squared.  A nonzero sum lies in
+// [2^-298, 2^257), inside the seed's range; zero gives zero (its seed is
+// taken at 1e-300), so there is no branch and no select.
 __device__ __forceinline__ double cabs64(float re, float im) {
     const double x = fma((double)re, (double)re, (double)im * (double)im);
-    const bool tiny = x < 1e-30, huge = x > 1e30;
-    const double xs = x * (tiny ? 0x1p200 : (huge ? 0x1p-200 : 1.0));
-    double y = (double)__builtin_amdgcn_rsqf((float)xs);
-    y = y * fma(-0.5 * xs * y, y, 1.5);
-    const double r = xs * y * (tiny ? 0x1p-100 : (huge ? 0x1p100 : 1.0));
-    return x == 0.0 ? 0.0 : r;
+    const double y = __builtin_amdgcn_rsq(fmax(x, 1e-300));
+    const double s = x * y;
+    return fma(s, fma(-s, 0.5 * y, 0.5), s);
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {

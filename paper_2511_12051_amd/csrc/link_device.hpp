@@ -150,7 +150,7 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) gi[r][j] = (live[r] && j < N) ? cabs64(c[r][j].x, c[r][j].y) : 0.0;
+        for (int j = 0; j < NJ; ++j) gi[r][j] = cabs64(c[r][j].x, c[r][j].y);  // c is zero outside N x N
     const bool do_emi = !use_evd && !invalid;
     const bool gfail = factor_g<16, R, NJ>(gi, N, l, do_emi, nullptr, nullptr);
     use_evd = use_evd || gfail;
