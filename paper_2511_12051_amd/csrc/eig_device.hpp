@@ -885,12 +885,12 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 __device__ __forceinline__ constexpr int acc_row(int v, int h) { return 8 * (v >> 2) + 4 * h + (v & 3); }
 
 // Operands of sweep step K for one accumulator pair (VALU part).  Row K
-// lives in register KV of the lanes of half KH; one v_permlane32_swap of
-// the real and imaginary registers in place leaves {Re r, Im r} in the
-// register of half KH (lane c: Re r_c, lane c + 32: Im r_c), which is
-// exactly the B operand of the real update, and {row K + 4 - 8 KH} in the
-// other; a second swap restores both.  The B operand of the imaginary
-// update has the halves exchanged.
+// lives in register KV of the lanes of half KH.  v_permlane32_swap a, b
+// exchanges the upper 32 lanes of a with the lower 32 lanes of b: applied to
+// copies of the real and imaginary registers it leaves {Re r, Im r} in the
+// copy of half KH (lane c: Re r_c, lane c + 32: Im r_c), which is exactly
+// the B operand of the real update; with the operands exchanged it leaves
+// {Im r, Re r}, the B operand of the imaginary update.
 template <int K>
 __device__ __forceinline__ void sweep_operands(f32x16& ar, f32x16& ai, int lane, float& are, float& bre,
                                                float& aim, float& bim, bool& pd) {
@@ -899,15 +899,9 @@ __device__ __forceinline__ void sweep_operands(f32x16& ar, f32x16& ai, int lane,
     float x = ar[KV], y = ai[KV];
     asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
     bre = KH ? y : x;  // lane c: Re r_c, lane c + 32: Im r_c
-    {
-        float u = x, w = y;  // restore the accumulators
-        asm volatile("v_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(u), "+v"(w));
-        ar[KV] = u;
-        ai[KV] = w;
-    }
-    float lo = bre, hi = bre;
-    asm volatile("v_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(lo), "+v"(hi));
-    bim = h ? lo : hi;  // lane c: Im r_c, lane c + 32: Re r_c
+    float u = ar[KV], w = ai[KV];  // the same swap with the operands exchanged
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(w), "+v"(u));
+    bim = KH ? u : w;  // lane c: Im r_c, lane c + 32: Re r_c
     const float p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bre), K));
     pd = pd && (p > 0.f) && (p <= 3.4e38f);
     const float rp = __builtin_amdgcn_rcpf(p);
