@@ -813,6 +813,7 @@ struct BTriLds {
     __device__ __forceinline__ void load(float2 (&m)[2][NJ], bool pred) const {
         if (pred) {
             const int ll = opaque_int(l), n = opaque_uniform(N);
+            __builtin_assume(n >= kMinN<NJ> && n <= NJ);
             const int ub[2] = {up_base(ll, 0), up_base(ll, 1)}, lb[2] = {lo_base(ll, 0), lo_base(ll, 1)};
             load_steps<0>(m, ub, lb, ll, n);
         }
@@ -854,6 +855,7 @@ struct BTriLds {
     // y = B x for this lane's two rows
     __device__ __forceinline__ void apply(const float2 (&x)[2], float2 (&y)[2]) const {
         const int ll = opaque_int(l), n = opaque_uniform(N);
+        __builtin_assume(n >= kMinN<NJ> && n <= NJ);
         const int ub[2] = {up_base(ll, 0), up_base(ll, 1)}, lb[2] = {lo_base(ll, 0), lo_base(ll, 1)};
         y[0] = y[1] = make_float2(0.f, 0.f);
         apply_steps<0>(ub, lb, ll, n, x, y);

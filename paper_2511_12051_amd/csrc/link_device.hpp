@@ -51,6 +51,9 @@ __device__ __forceinline__ void link_body(const LinkArgs& a, int64_t block, int 
     const int stid = (slot << 6) | (tid & 63);
 
     const int N = opaque_uniform(__builtin_amdgcn_readfirstlane(a.N));
+    // every caller picks NJ as N rounded up to a multiple of four (N <= 12:
+    // NJ = 12), so the per-column tests j < N are known true below NJ - 3
+    __builtin_assume(N >= kMinN<NJ> && N <= NJ);
     const int64_t pix = (block * (kBlock / 64) + wave) * GPW + grp;
     const bool active = pix < a.npix;
     bool live[R];
