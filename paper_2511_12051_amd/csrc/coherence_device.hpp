@@ -264,6 +264,16 @@ __device__ __forceinline__ void transpose_read(float* S, const typename Acc<NT>:
     wave_sync();
 }
 
+// Marks R loaded values as used here (R a multiple of 4): loads whose values
+// are only used under a per-entry condition can be moved into one branch
+// each, where each waits for its data before the next is issued; placed
+// after a run of loads, this keeps them back to back with one wait.
+template <int R>
+__device__ __forceinline__ void keep_loaded(float (&v)[R]) {
+#pragma unroll
+    for (int k = 0; k < R; k += 4) asm volatile("" : "+v"(v[k]), "+v"(v[k + 1]), "+v"(v[k + 2]), "+v"(v[k + 3]));
+}
+
 // Normalise and store one pixel's matrix from Re/Im in accumulator layout.
 template <int NT, bool SPLIT>
 __device__ __forceinline__ void store_pixel(const CohArgs& a, float* S, const typename Acc<NT>::T& re,
@@ -285,11 +295,15 @@ __device__ __forceinline__ void store_pixel(const CohArgs& a, float* S, const ty
     if (a.diag && lane < NT && j < N) a.diag[pix * N + j] = dj;
     const int packed = a.packed;
     float2* out = a.coh + pix * (int64_t)(packed ? (N * (N + 1)) >> 1 : N * N);
+    float di[Acc<NT>::R];  // diagonal entries of this lane's rows (row < NT)
+#pragma unroll
+    for (int v = 0; v < Acc<NT>::R; ++v) di[v] = diag[Acc<NT>::row(lane, v)];
+    keep_loaded(di);
 #pragma unroll
     for (int v = 0; v < Acc<NT>::R; ++v) {
         const int i = Acc<NT>::row(lane, v);
         if (i < N && j < N && (!packed || i <= j)) {
-            const float isi = __builtin_amdgcn_rsqf(diag[i]);
+            const float isi = __builtin_amdgcn_rsqf(di[v]);
             float2 c = make_float2(re[v] * isi * isj, im[v] * isi * isj);
             if (i == j) c = make_float2(1.f, 0.f);
             if (invalid) c = make_float2(__builtin_nanf(""), __builtin_nanf(""));
