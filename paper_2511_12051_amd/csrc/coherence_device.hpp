@@ -99,16 +99,22 @@ struct RowLoad {
     f32x4 v[kPfRows<NT>][kPfItems];
 };
 
-__device__ __forceinline__ f32x4 fetch_unit(const CohArgs& a, const float2* const* planes, uint32_t dp, int64_t y,
-                                           int64_t x0) {
+typedef __attribute__((address_space(1))) const float2 gfloat2;  // global memory
+typedef __attribute__((address_space(1))) const f32x4 gf32x4;
+
+// `plane` is the unit's image plane (planes[dp >> 16]), in global memory
+// (the explicit address space keeps the loads global loads even when the
+// pointer went through an opaque register copy).
+__device__ __forceinline__ f32x4 fetch_unit_at(const CohArgs& a, const float2* plane, uint32_t dp, int64_t y,
+                                              int64_t x0) {
     const Geometry& g = a.g;
-    const int d = (int)(dp >> 16), px = (int)(dp & 0xffffu);
+    const int px = (int)(dp & 0xffffu);
     const int64_t x = x0 + 2 * px;
     f32x4 z = {0.f, 0.f, 0.f, 0.f};
     if (y >= 0 && y < g.R) {
-        const float2* row = planes[d] + y * g.C;
+        gfloat2* row = (gfloat2*)plane + y * g.C;
         if (a.vec_rows && x >= 0 && x + 1 < g.C) {
-            z = *reinterpret_cast<const f32x4*>(row + x);  // 16-byte aligned pair
+            z = *reinterpret_cast<gf32x4*>(row + x);  // 16-byte aligned pair
         } else {
             if (x >= 0 && x < g.C) {
                 z[0] = row[x].x;
@@ -121,6 +127,31 @@ __device__ __forceinline__ f32x4 fetch_unit(const CohArgs& a, const float2* cons
         }
     }
     return z;
+}
+
+__device__ __forceinline__ f32x4 fetch_unit(const CohArgs& a, const float2* const* planes, uint32_t dp, int64_t y,
+                                           int64_t x0) {
+    return fetch_unit_at(a, planes[dp >> 16], dp, y, x0);
+}
+
+// Image planes of a thread's prefetched items, read from the plane table once
+// per kernel: the table sits in argument memory and a per-lane index makes
+// each read a vector memory load, which would otherwise put a dependent
+// round trip (and a wait for every load in flight) before each prefetch.
+struct ItemPlanes {
+    const float2* p[kPfItems];
+};
+
+__device__ __forceinline__ ItemPlanes item_planes(const float2* const* planes, const Items& it) {
+    ItemPlanes ip;
+#pragma unroll
+    for (int k = 0; k < kPfItems; ++k) ip.p[k] = planes[k < it.n ? it.dp[k] >> 16 : 0];
+    // redefine the pointers here, after their loads completed: otherwise the
+    // wait for them is placed at their first use inside the row loop, where
+    // it is repeated every row and waits for the stores and loads in flight
+#pragma unroll
+    for (int k = 0; k < kPfItems; ++k) asm volatile("" : "+v"(ip.p[k]));
+    return ip;
 }
 
 // Converts a pixel pair {re0, im0, re1, im1} into its 16-byte record and
@@ -165,14 +196,44 @@ __device__ __forceinline__ void load_rows(const CohArgs& a, const float2* const*
 
 // Start the global loads of the prefetched units of the next rows; they
 // complete while the current row's pixels are computed.
+// Start the global loads of the prefetched units of the next kPfRows rows;
+// they complete while the current row's pixels are computed.  Every slot is
+// loaded, at row and column indices clamped into the image (two 8-byte loads
+// per unit), with no branch: the number of loads in flight is then the same
+// on every path, so a later wait for a load issued before them (the first
+// pixel's mask) can leave them in flight.  Out-of-image entries are zeroed
+// at commit time (fix_unit), slots beyond the thread's items or the rows
+// the next output row needs are never committed.
+__device__ __forceinline__ f32x4 fetch_clamped(const CohArgs& a, const float2* plane, uint32_t dp, int64_t y,
+                                               int64_t x0) {
+    const Geometry& g = a.g;
+    const int64_t x = x0 + 2 * (int)(dp & 0xffffu);
+    const int64_t yc = y < 0 ? 0 : (y >= g.R ? g.R - 1 : y);
+    const int64_t xa = x < 0 ? 0 : (x >= g.C ? g.C - 1 : x);
+    const int64_t xb = x + 1 < 0 ? 0 : (x + 1 >= g.C ? g.C - 1 : x + 1);
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) const f32x2 gf32x2;
+    gf32x2* row = (gf32x2*)plane + yc * g.C;
+    const f32x2 u = row[xa], v = row[xb];
+    return f32x4{u[0], u[1], v[0], v[1]};
+}
+
+// Zeroes the entries of a clamped unit that lie outside the image.
+__device__ __forceinline__ f32x4 fix_unit(const CohArgs& a, uint32_t dp, int64_t y, int64_t x0, f32x4 z) {
+    const Geometry& g = a.g;
+    const int64_t x = x0 + 2 * (int)(dp & 0xffffu);
+    const bool yin = y >= 0 && y < g.R;
+    const bool in0 = yin && x >= 0 && x < g.C, in1 = yin && x + 1 >= 0 && x + 1 < g.C;
+    return f32x4{in0 ? z[0] : 0.f, in0 ? z[1] : 0.f, in1 ? z[2] : 0.f, in1 ? z[3] : 0.f};
+}
+
 template <int NT>
-__device__ __forceinline__ void prefetch_rows(const CohArgs& a, const float2* const* planes, const Items& it,
-                                              RowLoad<NT>& pf, int64_t y_first, int nrows, int64_t x0) {
+__device__ __forceinline__ void prefetch_rows(const CohArgs& a, const ItemPlanes& ip, const Items& it,
+                                              RowLoad<NT>& pf, int64_t y_first, int64_t x0) {
 #pragma unroll
     for (int r = 0; r < kPfRows<NT>; ++r)
 #pragma unroll
-        for (int k = 0; k < kPfItems; ++k)
-            if (r < nrows && k < it.n) pf.v[r][k] = fetch_unit(a, planes, it.dp[k], y_first + r, x0);
+        for (int k = 0; k < kPfItems; ++k) pf.v[r][k] = fetch_clamped(a, ip.p[k], it.dp[k], y_first + r, x0);
 }
 
 template <int NT, bool SPLIT>
@@ -186,7 +247,7 @@ __device__ __forceinline__ void commit_rows(const CohArgs& a, const float2* cons
         if (r < nrows) {
 #pragma unroll
             for (int k = 0; k < kPfItems; ++k)
-                if (k < it.n) store_unit<SPLIT>(a, lds, it.dp[k], slot, pf.v[r][k]);
+                if (k < it.n) store_unit<SPLIT>(a, lds, it.dp[k], slot, fix_unit(a, it.dp[k], y_first + r, x0, pf.v[r][k]));
             slot = next_slot(slot, a.g.wy);
         }
     }
@@ -481,6 +542,7 @@ __device__ __forceinline__ void coherence_body(const CohArgs& a, const float2* c
     };
     RowLoad<NT> pf;
     const Items items = make_items(a, nthreads);
+    const ItemPlanes iplanes = item_planes(planes, items);
     // prologue: the full window of the first output row
     load_rows<SPLIT>(a, planes, items, lds_words, oy0 * g.sy + g.sy / 2 - g.hy, g.wy, x0);
     __syncthreads();
@@ -490,15 +552,25 @@ __device__ __forceinline__ void coherence_body(const CohArgs& a, const float2* c
         const int64_t next_first = (cy + g.hy + 1) > (cy + g.sy - g.hy) ? (cy + g.hy + 1) : (cy + g.sy - g.hy);
         const int next_rows = (int)((cy + g.sy + g.hy) - next_first + 1);
         const bool more = oy + 1 < oy1;
-        if (more) prefetch_rows<NT>(a, planes, items, pf, next_first, next_rows, x0);
-        const int s0 = first_slot(oy);
+        // The first pixel's mask is requested before the row prefetch and
+        // waited for right after it is issued: loads complete in order, so
+        // that wait leaves the prefetch in flight.  Each value is redefined
+        // once its load has arrived (an empty asm), so that no wait for the
+        // prefetch is merged into the paths that follow.
         int64_t ox = ox0 + wave;
-        uint32_t mw = 0;
-        if (ox < ox1 && lane < g.nw) mw = a.mask[(oy * g.oC + ox) * g.nw + lane];
+        uint32_t mfirst = 0;
+        if (ox < ox1 && lane < g.nw) mfirst = a.mask[(oy * g.oC + ox) * g.nw + lane];
+        prefetch_rows<NT>(a, iplanes, items, pf, next_first, x0);  // unused after the last row
+        asm volatile("" : "+v"(mfirst));
+        const int s0 = first_slot(oy);
         for (; ox < ox1; ox += nwaves) {
-            const uint32_t mcur = mw;
-            if (ox + nwaves < ox1 && lane < g.nw) mw = a.mask[(oy * g.oC + ox + nwaves) * g.nw + lane];
-            const int npad = build_pairs<SPLIT>(a, wave_area, ox, x0, s0, mcur, PPK, lane);
+            uint32_t mw = mfirst;
+            if (ox != ox0 + wave) {  // later pixels of a strip wider than the wave count
+                uint32_t m = lane < g.nw ? a.mask[(oy * g.oC + ox) * g.nw + lane] : 0u;
+                asm volatile("" : "+v"(m));
+                mw = m;
+            }
+            const int npad = build_pairs<SPLIT>(a, wave_area, ox, x0, s0, mw, PPK, lane);
             wave_sync();
             typename Acc<NT>::T re, im;
             pixel_gram<NT, SPLIT>(a, lds_words, wave_area, npad, lane, re, im, S);
