@@ -383,7 +383,8 @@ __device__ __forceinline__ void pixel_gram(const CohArgs& a, const void* lds, co
     const bool live = d < a.N;
     const int g = lane / NT;  // k-group of this lane
     // Dead rows (image index >= N) read a valid plane and are masked to zero
-    // on the A side; their garbage B columns are never stored.
+    // (on the A side, and on the B side too in split BF16); their B columns
+    // are never stored.
     const int dd = live ? d : a.N - 1;
     const uint32_t live_mask = live ? 0xffffffffu : 0u;
     AT whh = {}, v1 = {};
@@ -392,7 +393,7 @@ __device__ __forceinline__ void pixel_gram(const CohArgs& a, const void* lds, co
         // MFMAs, so no transpose (and no transpose scratch in LDS):
         //   Re A = sum s (rh rh + rh rl + rl rh + ih ih + ih il + il ih)
         //   Im A = sum s (ih rh + ih rl + il rh) - sum s (rh ih + rh il + rl ih)
-        // with the SHP bit on the A operand of every product (row index m).
+        // with the SHP bit on both operands of every product.
         AT re1 = {}, imn = {};
         constexpr int PPK = 8;  // pairs per k-step
         const u32x4* P = reinterpret_cast<const u32x4*>(lds) + dd * a.plane;
@@ -407,29 +408,28 @@ __device__ __forceinline__ void pixel_gram(const CohArgs& a, const void* lds, co
             }
             const uint32_t m0 = e01[1] & live_mask, m1 = e01[3] & live_mask;
             const uint32_t m2 = e23[1] & live_mask, m3 = e23[3] & live_mask;
-            const u32x4 rh = {q0[0], q1[0], q2[0], q3[0]}, rl = {q0[1], q1[1], q2[1], q3[1]};
-            const u32x4 ih = {q0[2], q1[2], q2[2], q3[2]}, il = {q0[3], q1[3], q2[3], q3[3]};
+            // Both operands masked: s in {0, 1}, so (s x_m)(s x_n) = s x_m x_n
+            // exactly, and the masked words go straight into the operand
+            // registers (no unmasked copies are assembled).
             const u32x4 rhm = {q0[0] & m0, q1[0] & m1, q2[0] & m2, q3[0] & m3};
             const u32x4 rlm = {q0[1] & m0, q1[1] & m1, q2[1] & m2, q3[1] & m3};
             const u32x4 ihm = {q0[2] & m0, q1[2] & m1, q2[2] & m2, q3[2] & m3};
             const u32x4 ilm = {q0[3] & m0, q1[3] & m1, q2[3] & m2, q3[3] & m3};
-            const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh), Rl = __builtin_bit_cast(bf16x8, rl);
-            const bf16x8 Ih = __builtin_bit_cast(bf16x8, ih), Il = __builtin_bit_cast(bf16x8, il);
             const bf16x8 Rhm = __builtin_bit_cast(bf16x8, rhm), Rlm = __builtin_bit_cast(bf16x8, rlm);
             const bf16x8 Ihm = __builtin_bit_cast(bf16x8, ihm), Ilm = __builtin_bit_cast(bf16x8, ilm);
             // four accumulation chains, interleaved
-            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Rh, whh, 0, 0, 0);
-            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Rh, v1, 0, 0, 0);
-            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Rl, re1, 0, 0, 0);
-            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Ih, imn, 0, 0, 0);
-            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rlm, Rh, whh, 0, 0, 0);
-            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Rl, v1, 0, 0, 0);
-            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Ih, re1, 0, 0, 0);
-            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Il, imn, 0, 0, 0);
-            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Il, whh, 0, 0, 0);
-            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ilm, Rh, v1, 0, 0, 0);
-            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ilm, Ih, re1, 0, 0, 0);
-            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rlm, Ih, imn, 0, 0, 0);
+            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Rhm, whh, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Rhm, v1, 0, 0, 0);
+            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Rlm, re1, 0, 0, 0);
+            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Ihm, imn, 0, 0, 0);
+            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rlm, Rhm, whh, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Rlm, v1, 0, 0, 0);
+            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Ihm, re1, 0, 0, 0);
+            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rhm, Ilm, imn, 0, 0, 0);
+            whh = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ihm, Ilm, whh, 0, 0, 0);
+            v1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ilm, Rhm, v1, 0, 0, 0);
+            re1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ilm, Ihm, re1, 0, 0, 0);
+            imn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Rlm, Ihm, imn, 0, 0, 0);
             e01 = n01;
             e23 = n23;
         }
@@ -452,13 +452,15 @@ __device__ __forceinline__ void pixel_gram(const CohArgs& a, const void* lds, co
             }
             const uint32_t m0 = e01[1] & live_mask, m1 = e01[3] & live_mask;
             const uint32_t m2 = e23[1] & live_mask, m3 = e23[3] & live_mask;
-            const u32x4 rh = {q0[0], q1[0], q2[0], q3[0]}, rl = {q0[1], q1[1], q2[1], q3[1]};
-            const u32x4 ih = {q0[2], q1[2], q2[2], q3[2]}, il = {q0[3], q1[3], q2[3], q3[3]};
+            // both operands masked (s x_m)(s x_n) = s x_m x_n, s in {0, 1}: the
+            // masked words go straight into the operand registers
             const u32x4 rhm = {q0[0] & m0, q1[0] & m1, q2[0] & m2, q3[0] & m3};
+            const u32x4 rlm = {q0[1] & m0, q1[1] & m1, q2[1] & m2, q3[1] & m3};
             const u32x4 ihm = {q0[2] & m0, q1[2] & m1, q2[2] & m2, q3[2] & m3};
-            const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh), Rl = __builtin_bit_cast(bf16x8, rl);
-            const bf16x8 Ih = __builtin_bit_cast(bf16x8, ih), Il = __builtin_bit_cast(bf16x8, il);
-            const bf16x8 Rm = __builtin_bit_cast(bf16x8, rhm), Im = __builtin_bit_cast(bf16x8, ihm);
+            const u32x4 ilm = {q0[3] & m0, q1[3] & m1, q2[3] & m2, q3[3] & m3};
+            const bf16x8 Rh = __builtin_bit_cast(bf16x8, rhm), Rl = __builtin_bit_cast(bf16x8, rlm);
+            const bf16x8 Ih = __builtin_bit_cast(bf16x8, ihm), Il = __builtin_bit_cast(bf16x8, ilm);
+            const bf16x8 Rm = Rh, Im = Ih;
             // the four accumulation chains are interleaved so that no MFMA
             // waits on the one just issued
             if constexpr (NT == 16) {
