@@ -7,9 +7,9 @@
 // three real Gram-type products X diag(s) Y^T whose rows are the images
 // (at most 16 or 32) and whose reduction runs over window samples - exactly
 // the operand shape of an MFMA, with A- and B-fragments read by the same
-// lane.  The SHP weight is applied by zeroing masked samples: of the A
-// operand only in FP32, of both operands in split BF16 (s in {0, 1}, so
-// (s x_m)(s x_n) = s x_m x_n exactly).
+// lane.  The SHP weight is applied by zeroing masked samples of both
+// operands (s in {0, 1}, so (s x_m)(s x_n) = s x_m x_n exactly, and a
+// non-finite sample outside the SHPs adds an exact zero).
 //
 // Plain FP32: v_mfma_f32_{16x16x4,32x32x2}f32 on r, i directly.
 // Split BF16: each value x = hi + lo with hi = bf16(x), lo = bf16(x - hi)

@@ -383,8 +383,7 @@ __device__ __forceinline__ void pixel_gram(const CohArgs& a, const void* lds, co
     const bool live = d < a.N;
     const int g = lane / NT;  // k-group of this lane
     // Dead rows (image index >= N) read a valid plane and are masked to zero
-    // (on the A side, and on the B side too in split BF16); their B columns
-    // are never stored.
+    // on both operand sides; their columns are never stored.
     const int dd = live ? d : a.N - 1;
     const uint32_t live_mask = live ? 0xffffffffu : 0u;
     AT whh = {}, v1 = {};
@@ -502,14 +501,17 @@ __device__ __forceinline__ void pixel_gram(const CohArgs& a, const void* lds, co
             const bool on = live && ((e[1] >> half) & 1u);
             const float r = z[0], im_ = z[1];
             const float rm = on ? r : 0.f, imm = on ? im_ : 0.f;
+            // the SHP bit on both operands: (s x_m)(s x_n) = s x_m x_n, and a
+            // non-finite sample outside the SHPs (sharing a record with one)
+            // contributes an exact zero instead of 0 * NaN
             if constexpr (NT == 16) {
-                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, r, whh, 0, 0, 0);
-                v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, im_, v1, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(imm, im_, whh, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, rm, whh, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, imm, v1, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(imm, imm, whh, 0, 0, 0);
             } else {
-                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, r, whh, 0, 0, 0);
-                v1 = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, im_, v1, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(imm, im_, whh, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, rm, whh, 0, 0, 0);
+                v1 = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, imm, v1, 0, 0, 0);
+                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(imm, imm, whh, 0, 0, 0);
             }
         }
         re = whh;

@@ -286,6 +286,33 @@ def test_nodata_pixels_are_invalid_and_ragged_grid(gpu_lib):
     assert np.all(ph.cpu().numpy()[:, inval] == 1)
 
 
+def test_nan_nodata_outside_shps_is_excluded(gpu_lib):
+    """A NaN nodata block: never an SHP of another pixel (Sec. 3.1, nodata
+    reading), so the pixels whose windows reach it have the oracle's finite
+    coherence in both precisions, also where a NaN pixel and an SHP share a
+    pixel-pair record; only the pixels centred on the block are invalid."""
+    wl = synth.crop("tiny", 37, 43)
+    z = synth.make_stack(wl, seed=26)
+    z[:, 5:9, 7:12] = complex(float("nan"), float("nan"))
+    window = (3, 2, 2, 3)
+    zc = z.cuda()
+    mean, var = gpu_lib.amplitude_stats(zc)
+    mask, count = gpu_lib.shp_select(mean, var, wl.n_new, window, 1e-3)
+    r = O.link_ministack(z.numpy(), 0, window, 1e-3, 0)
+    np.testing.assert_array_equal(mask.cpu().numpy().view(np.uint32), r["mask"])
+    P = len(r["coh"])
+    fin = np.all(np.isfinite(r["coh"].reshape(P, -1)), axis=1)
+    assert fin.sum() > 0 and (~fin).sum() > 0
+    for prec in ("fp32", "bf16"):
+        coh = gpu_lib.estimate_coherence(zc, mask, window, precision=prec)
+        ph, lam, flags = gpu_lib.phase_link(coh, ref=0)
+        g = coh.cpu().numpy().reshape(P, -1)
+        assert np.all(np.isfinite(g[fin])), prec
+        assert np.all(np.isnan(g[~fin])), prec
+        assert np.max(np.abs(g[fin] - r["coh"].reshape(P, -1)[fin])) < COH_TOL, prec
+        np.testing.assert_array_equal(flags.cpu().numpy() == 2, r["link"]["flag"] == 2)
+
+
 def test_max_images_and_single_image(gpu_lib):
     wl = synth.crop("tiny", 24, 24)
     rng = np.random.default_rng(24)
