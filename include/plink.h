@@ -173,7 +173,12 @@ pl_status pl_estimate_coherence(const pl_c64* stack, int32_t N, int64_t R, int64
  * |sum_{i<k} exp(j(arg C_ik - (phi_i - phi_k)))| / (N(N-1)/2), with arg 0 = 0,
  * 1 for N = 1 and 0 at invalid pixels; flags: [npix] or NULL (PL_FLAG_*);
  * invalid pixels (non-finite C) get phasors 1.  For N > 16 C is read as the
- * Hermitian matrix of its upper triangle.
+ * Hermitian matrix of its upper triangle.  The iteration of a pixel stops when
+ * its unit iterate changes by less than 2e-6 (or contracts fast enough for
+ * the remaining error to be below that) and after at most 96 steps; a pixel
+ * that reaches the cap keeps its last iterate and its normal flag, and is
+ * counted in counters[PL_CNT_NOT_CONVERGED] (a few per million pixels on the
+ * synthetic workloads).
  * counters: optional.  npix = 0 is a no-op (pointers may then be NULL). */
 pl_status pl_phase_link(const pl_c64* coh, int32_t N, int64_t npix, int32_t ref_idx,
                         pl_link_method method, pl_c64* phasors, float* phase, float* lambda,
