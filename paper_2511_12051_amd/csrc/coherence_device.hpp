@@ -492,26 +492,51 @@ __device__ __forceinline__ void pixel_gram(const CohArgs& a, const void* lds, co
         constexpr int SPK = NT == 16 ? 4 : 2;  // samples per k-step
         typedef float f32x2 __attribute__((ext_vector_type(2)));
         typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        constexpr int STEP = SPK / 2;  // pairs per k-step
+        constexpr int U = 8;           // k-steps per batch
         const f32x2* P = reinterpret_cast<const f32x2*>(lds) + 2 * dd * a.plane;
         const int half = g & 1;
         const int eoff = g >> 1;  // which pair of the k-step (16x16x4 only)
-        for (int ks = 0; ks < npad; ks += SPK / 2) {
-            const u32x2 e = *reinterpret_cast<const u32x2*>(table + 2 * (ks + eoff));
-            const f32x2 z = P[2 * e[0] + half];  // {re, im} of this lane's sample
-            const bool on = live && ((e[1] >> half) & 1u);
-            const float r = z[0], im_ = z[1];
-            const float rm = on ? r : 0.f, imm = on ? im_ : 0.f;
-            // the SHP bit on both operands: (s x_m)(s x_n) = s x_m x_n, and a
-            // non-finite sample outside the SHPs (sharing a record with one)
-            // contributes an exact zero instead of 0 * NaN
-            if constexpr (NT == 16) {
-                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, rm, whh, 0, 0, 0);
-                v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, imm, v1, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_16x16x4f32(imm, imm, whh, 0, 0, 0);
-            } else {
-                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, rm, whh, 0, 0, 0);
-                v1 = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, imm, v1, 0, 0, 0);
-                whh = __builtin_amdgcn_mfma_f32_32x32x2f32(imm, imm, whh, 0, 0, 0);
+        // Each sample needs two dependent LDS reads (its list entry, then the
+        // record): a batch of U k-steps issues its U entry reads, then its U
+        // sample reads, then its MFMAs in the plain k-step order, so two LDS
+        // round trips serve U k-steps.  Reads past the end of the list are
+        // clamped to its last step and their products skipped.
+        const u32x2* T = reinterpret_cast<const u32x2*>(table) + eoff;
+        const int lastc = npad > STEP ? npad - STEP : 0;
+        for (int ks = 0; ks < npad; ks += U * STEP) {
+            u32x2 e[U];
+            f32x2 z[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = ks + u * STEP;
+                e[u] = T[k < lastc ? k : lastc];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) z[u] = P[2 * e[u][0] + half];  // {re, im} of this lane's sample
+            // the reads are used here, before the first product: otherwise
+            // the compiler sinks each into its k-step's branch below, which
+            // serialises them again
+#pragma unroll
+            for (int u = 0; u < U; ++u) asm volatile("" ::"v"(z[u]), "v"(e[u][1]));
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (ks + u * STEP >= npad) break;  // uniform
+                const bool on = live && ((e[u][1] >> half) & 1u);
+                const float r = z[u][0], im_ = z[u][1];
+                const float rm = on ? r : 0.f, imm = on ? im_ : 0.f;
+                // the SHP bit on both operands: (s x_m)(s x_n) = s x_m x_n, and a
+                // non-finite sample outside the SHPs (sharing a record with one)
+                // contributes an exact zero instead of 0 * NaN
+                if constexpr (NT == 16) {
+                    whh = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, rm, whh, 0, 0, 0);
+                    v1 = __builtin_amdgcn_mfma_f32_16x16x4f32(rm, imm, v1, 0, 0, 0);
+                    whh = __builtin_amdgcn_mfma_f32_16x16x4f32(imm, imm, whh, 0, 0, 0);
+                } else {
+                    whh = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, rm, whh, 0, 0, 0);
+                    v1 = __builtin_amdgcn_mfma_f32_32x32x2f32(rm, imm, v1, 0, 0, 0);
+                    whh = __builtin_amdgcn_mfma_f32_32x32x2f32(imm, imm, whh, 0, 0, 0);
+                }
             }
         }
         re = whh;
