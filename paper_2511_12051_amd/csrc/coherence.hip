@@ -74,6 +74,19 @@ const void* coherence_fn(int nt, bool split, bool batch) {
     return split ? kernel_of<32, true>(batch) : kernel_of<32, false>(batch);
 }
 
+// compute units of the current device (queried once per device)
+int device_cus() {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (!cus[dev]) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 1;
+        cus[dev] = c;
+    }
+    return cus[dev];
+}
+
 }  // namespace
 
 size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req, int64_t* blocks) {
@@ -112,11 +125,34 @@ size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req
         if (reinterpret_cast<uintptr_t>(a.t.p[d]) & 15) a.vec_rows = 0;
     a.n_strips = (g.oC + chosen - 1) / chosen;
     int64_t rows = rows_req;
-    if (rows <= 0) {  // enough workgroups to fill the chip several times over
-        rows = ((a.oy_hi - a.oy_lo) * a.n_strips + 2047) / 2048;
-        if (rows < 4) rows = 4;
-    }
     const int64_t nrows = a.oy_hi - a.oy_lo;
+    if (rows <= 0) {  // enough workgroups to fill the chip several times over
+        rows = (nrows * a.n_strips + 2047) / 2048;
+        if (rows < 4) rows = 4;
+        // Each CU holds lds_cap / lds workgroups at a time, so the grid runs in
+        // rounds of that many per CU; a last round that is nearly empty still
+        // costs about one workgroup's duration.  Among band counts near this
+        // one, take the one that best fills the last round, weighed against
+        // the prologue of each band (its first wy - sy rows)
+        const int64_t slots = (int64_t)device_cus() * (int64_t)(lds_cap / lds > 0 ? lds_cap / lds : 1);
+        const int64_t nb0 = (nrows + rows - 1) / rows;
+        if (a.n_strips * nb0 >= 4 * slots) {
+            double best = -1.0;
+            int64_t best_rows = rows;
+            for (int64_t nb = (nb0 + 1) / 2; nb <= 3 * nb0 && nb <= nrows; ++nb) {
+                const int64_t r = (nrows + nb - 1) / nb;
+                const double rounds = (double)(a.n_strips * ((nrows + r - 1) / r)) / (double)slots;
+                const double fill = rounds / std::ceil(rounds);
+                const double pro = (double)(g.wy > g.sy ? g.wy - g.sy : 0) / ((double)r * g.sy);
+                const double score = fill / (1.0 + pro);
+                if (score > best + 1e-9) {
+                    best = score;
+                    best_rows = r;
+                }
+            }
+            rows = best_rows;
+        }
+    }
     if (rows > nrows) rows = nrows;
     a.rows_per_wg = (int)rows;
     *blocks = a.n_strips * ((nrows + rows - 1) / rows);
