@@ -20,17 +20,33 @@ __device__ __forceinline__ void glrt_body(const GlrtArgs& a, int64_t bx, int64_t
     const int64_t y0 = oy0 * g.sy + g.sy / 2 - g.hy;
     const int64_t x0 = ox0 * g.sx + g.sx / 2 - g.hx;
     const int nt = a.tw * a.th;
-    for (int i = tid; i < nt; i += nthreads) {
-        int ly = i / a.tw, lx = i - ly * a.tw;
-        int64_t y = y0 + ly, x = x0 + lx;
-        double s = __builtin_nan("");
-        if (y >= 0 && y < g.R && x >= 0 && x < g.C) {
-            int64_t p = y * g.C + x;
-            double m = a.mean[p], v = a.var[p];
-            double sv = 0.5 * fma(m, m, v);
-            if (sv > 0.0 && sv <= 1.7976931348623157e308) s = sv;
+    // The tile is staged kU elements per thread at a time: their loads are
+    // issued together (at clamped in-image indices, so without branches)
+    // before any is used, instead of one load pair and one wait per element.
+    constexpr int kU = 8;
+    for (int i0 = tid; i0 < nt; i0 += kU * nthreads) {
+        double m[kU], v[kU];
+        bool in[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * nthreads;
+            const int ly = i / a.tw, lx = i - ly * a.tw;
+            const int64_t y = y0 + ly, x = x0 + lx;
+            in[u] = i < nt && y >= 0 && y < g.R && x >= 0 && x < g.C;
+            const int64_t p = in[u] ? y * g.C + x : 0;
+            m[u] = a.mean[p];
+            v[u] = a.var[p];
         }
-        s_tile[i] = s;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int i = i0 + u * nthreads;
+            double s = __builtin_nan("");
+            if (in[u]) {
+                const double sv = 0.5 * fma(m[u], m[u], v[u]);
+                if (sv > 0.0 && sv <= 1.7976931348623157e308) s = sv;
+            }
+            if (i < nt) s_tile[i] = s;
+        }
     }
     __syncthreads();
 
