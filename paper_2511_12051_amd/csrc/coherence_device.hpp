@@ -356,18 +356,33 @@ __device__ __forceinline__ void store_pixel(const CohArgs& a, float* S, const ty
     if (a.diag && lane < NT && j < N) a.diag[pix * N + j] = dj;
     const int packed = a.packed;
     float2* out = a.coh + pix * (int64_t)(packed ? (N * (N + 1)) >> 1 : N * N);
-    float di[Acc<NT>::R];  // diagonal entries of this lane's rows (row < NT)
+    if (invalid) {  // uniform: some image without power over the SHPs, or a non-finite sum
 #pragma unroll
-    for (int v = 0; v < Acc<NT>::R; ++v) di[v] = diag[Acc<NT>::row(lane, v)];
-    keep_loaded(di);
+        for (int v = 0; v < Acc<NT>::R; ++v) {
+            const int i = Acc<NT>::row(lane, v);
+            if (i < N && j < N && (!packed || i <= j))
+                out[packed ? ((i * (2 * N - i - 1)) >> 1) + j : i * N + j] =
+                    make_float2(__builtin_nanf(""), __builtin_nanf(""));
+        }
+        wave_sync();
+        return;
+    }
+    // each row's reciprocal square root is formed once (by the lanes of its
+    // column) and shared through the diagonal scratch
+    wave_sync();  // every lane has read its diagonal entry
+    diag[j] = isj;
+    wave_sync();
+    float si[Acc<NT>::R];  // 1 / sqrt of the diagonal entries of this lane's rows (row < NT)
+#pragma unroll
+    for (int v = 0; v < Acc<NT>::R; ++v) si[v] = diag[Acc<NT>::row(lane, v)];
+    keep_loaded(si);
 #pragma unroll
     for (int v = 0; v < Acc<NT>::R; ++v) {
         const int i = Acc<NT>::row(lane, v);
         if (i < N && j < N && (!packed || i <= j)) {
-            const float isi = __builtin_amdgcn_rsqf(di[v]);
+            const float isi = si[v];
             float2 c = make_float2(re[v] * isi * isj, im[v] * isi * isj);
             if (i == j) c = make_float2(1.f, 0.f);
-            if (invalid) c = make_float2(__builtin_nanf(""), __builtin_nanf(""));
             // packed: entry (i, j >= i) of the row-major upper triangle
             out[packed ? ((i * (2 * N - i - 1)) >> 1) + j : i * N + j] = c;
         }
