@@ -133,7 +133,8 @@ size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req
         // rounds of that many per CU; a last round that is nearly empty still
         // costs about one workgroup's duration.  Among band counts near this
         // one, take the one that best fills the last round, weighed against
-        // the prologue of each band (its first wy - sy rows)
+        // the prologue of each band (its first wy - sy rows, loaded three rows
+        // per batch, so about a third of the cost of as many computed rows)
         const int64_t slots = (int64_t)device_cus() * (int64_t)(lds_cap / lds > 0 ? lds_cap / lds : 1);
         const int64_t nb0 = (nrows + rows - 1) / rows;
         if (a.n_strips * nb0 >= 4 * slots) {
@@ -143,7 +144,7 @@ size_t coherence_args(CohArgs* ap, int nt, bool split, int txo_max, int rows_req
                 const int64_t r = (nrows + nb - 1) / nb;
                 const double rounds = (double)(a.n_strips * ((nrows + r - 1) / r)) / (double)slots;
                 const double fill = rounds / std::ceil(rounds);
-                const double pro = (double)(g.wy > g.sy ? g.wy - g.sy : 0) / ((double)r * g.sy);
+                const double pro = (double)(g.wy > g.sy ? g.wy - g.sy : 0) / (3.0 * (double)r * g.sy);
                 const double score = fill / (1.0 + pro);
                 if (score > best + 1e-9) {
                     best = score;

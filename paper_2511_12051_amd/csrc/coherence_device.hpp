@@ -181,21 +181,6 @@ __device__ __forceinline__ void store_unit(const CohArgs& a, void* lds, uint32_t
 
 __device__ __forceinline__ int next_slot(int s, int wy) { return s + 1 == wy ? 0 : s + 1; }
 
-// Synchronous staging of rows [y_first, y_first + nrows).
-template <bool SPLIT>
-__device__ __forceinline__ void load_rows(const CohArgs& a, const float2* const* planes, const Items& it, void* lds,
-                          int64_t y_first, int nrows, int64_t x0) {
-    int slot = ring_slot(y_first, a.g.wy);
-    for (int r = 0; r < nrows; ++r) {
-#pragma unroll
-        for (int k = 0; k < kMaxItems; ++k)
-            if (k < it.n) store_unit<SPLIT>(a, lds, it.dp[k], slot, fetch_unit(a, planes, it.dp[k], y_first + r, x0));
-        slot = next_slot(slot, a.g.wy);
-    }
-}
-
-// Start the global loads of the prefetched units of the next rows; they
-// complete while the current row's pixels are computed.
 // Start the global loads of the prefetched units of the next kPfRows rows;
 // they complete while the current row's pixels are computed.  Every slot is
 // loaded, at row and column indices clamped into the image (two 8-byte loads
@@ -587,8 +572,16 @@ __device__ __forceinline__ void coherence_body(const CohArgs& a, const float2* c
     RowLoad<NT> pf;
     const Items items = make_items(a, nthreads);
     const ItemPlanes iplanes = item_planes(planes, items);
-    // prologue: the full window of the first output row
-    load_rows<SPLIT>(a, planes, items, lds_words, oy0 * g.sy + g.sy / 2 - g.hy, g.wy, x0);
+    // prologue: the full window of the first output row, kPfRows rows per
+    // batch of loads (the same values in the same ring slots as row by row)
+    {
+        const int64_t yw = oy0 * g.sy + g.sy / 2 - g.hy;
+        for (int r0 = 0; r0 < g.wy; r0 += kPfRows<NT>) {
+            const int nr = g.wy - r0 < kPfRows<NT> ? g.wy - r0 : kPfRows<NT>;
+            prefetch_rows<NT>(a, iplanes, items, pf, yw + r0, x0);
+            commit_rows<NT, SPLIT>(a, planes, items, lds_words, pf, yw + r0, nr, x0);
+        }
+    }
     __syncthreads();
     for (int64_t oy = oy0; oy < oy1; ++oy) {
         const int64_t cy = oy * g.sy + g.sy / 2;
